@@ -1,0 +1,95 @@
+"""Pins of the oracle's EM algebra (Eq. 6-9) by invariants that any correct
+list-mode OS-EM iterate satisfies."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.workload("tiny")
+    act, mu = synth.phantom(w)
+    g = w.geom.as_dict()
+    mod = O.OracleModel(g, mu)
+    ev = synth.workload_events(w, n_events=2000)
+    H = mod.system_matrix(ev)
+    return w, g, mod, ev, H
+
+
+def test_count_conservation_and_nonnegativity(tiny):
+    # after a sub-iteration sum_q sens_q^(i) f_q = number of events in subset i
+    w, g, mod, ev, H = tiny
+    sens = mod.sensitivity(0)
+    rng = np.random.default_rng(0)
+    f = rng.uniform(0.1, 2.0, size=H.shape[1])
+    f_new, mean, skipped = O.subset_update(H, f, sens)
+    assert skipped == 0
+    assert np.all(f_new >= 0)
+    assert float(sens @ f_new) == pytest.approx(H.shape[0], rel=1e-12)
+    assert np.all(mean > 0)
+
+
+def test_log_likelihood_never_decreases_for_one_subset(tiny):
+    w, g, mod, ev, H = tiny
+    sens = mod.sensitivity(-1)[None, :]
+    _f, ll = O.os_lm_mlem(H, ev["angle"], sens, 12, np.ones(H.shape[1]), 1)
+    assert np.all(np.diff(ll) >= -1e-9 * np.abs(ll[:-1]))
+
+
+def test_update_is_degree_zero_homogeneous_and_scales_with_time(tiny):
+    w, g, mod, ev, H = tiny
+    sens = mod.sensitivity(0)
+    f = np.linspace(0.5, 1.5, H.shape[1])
+    a, _, _ = O.subset_update(H, f, sens)
+    b, _, _ = O.subset_update(H, 7.5 * f, sens)
+    np.testing.assert_allclose(a, b, rtol=1e-13)
+    g2 = dict(g, acq_time=3.0)
+    mod3 = O.OracleModel(g2, mod.mu)
+    c, _, _ = O.subset_update(mod3.system_matrix(ev), f, mod3.sensitivity(0))
+    np.testing.assert_allclose(c, a / 3.0, rtol=1e-12)
+
+
+def test_event_order_is_irrelevant(tiny):
+    w, g, mod, ev, H = tiny
+    sens = mod.sensitivity(0)
+    f = np.ones(H.shape[1])
+    perm = np.random.default_rng(9).permutation(H.shape[0])
+    a, _, _ = O.subset_update(H, f, sens)
+    b, _, _ = O.subset_update(H[perm], f, sens)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+def test_subsets_follow_angle_interleave_and_iteration_order(tiny):
+    # Eq. 9: sub-iteration i starts from the estimate of sub-iteration i-1;
+    # the first sub-iteration of an iteration starts from the previous
+    # iteration's last one.  Subset i holds the angles a with a mod N_s == i.
+    w, g, mod, ev, H = tiny
+    ns = 4
+    g4 = dict(g, n_subsets=ns)
+    m4 = O.OracleModel(g4, mod.mu)
+    sens = np.stack([m4.sensitivity(i) for i in range(ns)])
+    np.testing.assert_allclose(sens.sum(axis=0), m4.sensitivity(-1), rtol=1e-12)
+    f0 = np.ones(H.shape[1])
+    f_os, _ = O.os_lm_mlem(H, ev["angle"], sens, 2, f0, ns)
+    f = f0.copy()
+    for _t in range(2):
+        for i in range(ns):
+            rows = ev["angle"] % ns == i
+            f, _, _ = O.subset_update(H[rows], f, sens[i])
+    np.testing.assert_allclose(f_os, f, rtol=1e-13)
+    # one subset is plain LM-MLEM (Eq. 6)
+    f1, _ = O.os_lm_mlem(H, ev["angle"], m4.sensitivity(-1)[None, :], 1, f0, 1)
+    f_ref, _, _ = O.subset_update(H, f0, m4.sensitivity(-1))
+    np.testing.assert_allclose(f1, f_ref, rtol=1e-14)
+
+
+def test_zero_sensitivity_pixels_and_dead_events_are_handled():
+    H = np.array([[1.0, 0.0, 0.0], [0.0, 2.0, 0.0], [0.0, 0.0, 0.0]])
+    f = np.array([1.0, 1.0, 3.0])
+    sens = np.array([1.0, 2.0, 0.0])
+    f_new, mean, skipped = O.subset_update(H, f, sens)
+    assert skipped == 1                       # the third event has mean 0
+    assert f_new[2] == 3.0                    # zero sensitivity: unchanged
+    np.testing.assert_allclose(f_new[:2], [1.0, 0.5])
