@@ -1,0 +1,195 @@
+"""Benchmark: list-mode events/s per OSEM subset update on one MI355X.
+
+Workload (brain64): 64x64 pixels of 0.4 cm, skull ring (mu 0.25/cm) around
+brain (mu 0.15/cm, activity 1) with caudate/putamen ellipses at 8:1 uptake,
+128 detector bins of 0.2 cm x 120 angles over 360 degrees, 200k list-mode
+events over 100-175 keV from the Monte-Carlo acquisition, 8 subsets.
+
+One step is one global OS-LM-MLEM iteration: the 8 subset updates (forward
+projection, per-event means, backprojection, multiplicative update) over all
+events, inputs resident in HBM.  value = events per second = J / step time
+(the sum over subsets of J_i over the sum of t_i).  Table build, event
+ingest and the CPU baseline are timed outside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "list-mode events/s per OSEM subset update; surrogate vs exact at stated error"
+
+# MI355X: 256 CUs at 2.4 GHz; per CU and clock 64 lanes of FP32 FMA (packed
+# FP32 is not used) and 16 lanes of transcendentals (v_exp_f32 at quarter rate).
+N_CU, CLK = 256, 2.4e9
+FMA_LANES, TRANS_LANES = 64, 16
+FLOPS_PER_TERM = 5      # FMA (2) + exp2 (1) + FMA (2)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def mix_peak_terms_per_s():
+    # lane-cycles per term: 2 FMAs at 1 per lane-cycle, one exp2 at FMA/TRANS
+    cyc = 2.0 + FMA_LANES / TRANS_LANES
+    return N_CU * CLK * FMA_LANES / cyc
+
+
+def cpu_baseline(w, act, mu, ev, n_sample=1024, seed=11):
+    """The FP64 oracle on the host cores: one subset update (system rows,
+    forward, backprojection, update) for a seeded sample of subset 0's events."""
+    import numpy as np
+    import oracle as O
+    g = w.geom.as_dict()
+    t0 = time.time()
+    m = O.OracleModel(g, mu)
+    t_model = time.time() - t0
+    sel = np.nonzero(ev["angle"] % g["n_subsets"] == 0)[0]
+    idx = np.sort(np.random.default_rng(seed).choice(sel, min(n_sample, sel.size), replace=False))
+    sub = {k: ev[k][idx] for k in ("angle", "u_bin", "energy")}
+    f = np.ones(len(m.support))
+    sens = m.sensitivity(0)
+    t0 = time.time()
+    H = m.system_matrix(sub)
+    O.subset_update(H, f, sens)
+    dt = time.time() - t0
+    return {"value": len(idx) / dt, "unit": "events/s", "cores": m.n_threads, "kind": "oracle",
+            "sample": f"{len(idx)} seeded events of subset 0 of brain64: FP64 system rows, "
+                      f"forward, backprojection and update ({dt:.1f} s wall on {m.n_threads} "
+                      f"threads; model build {t_model:.1f} s not counted)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--event-tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is event sharding with one all-reduce per sub-iteration)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2002_12471_amd import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_2002_12471_amd import lmosem as L
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("brain64")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    log("generating events")
+    ev = synth.workload_events(w)
+    J = len(ev["angle"])
+    evd = L.events_to_device(ev, dev)
+    mu_d = torch.as_tensor(mu, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    log("building tables")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx = L.Context(g, mu_d, stream)
+    torch.cuda.synchronize()
+    t_create = time.time() - t0
+    if args.event_tile:
+        ctx.set_tuning(args.event_tile)
+    t0 = time.time()
+    evs = L.lmosem_events_load(ctx.handle, evd)
+    torch.cuda.synchronize()
+    t_load = time.time() - t0
+    img = torch.as_tensor((mu > 0).astype(np.float32), device=dev).contiguous()
+
+    log("warm-up")
+    for _ in range(args.warmup):
+        L.lmosem_iterate(ctx.handle, evs, 1, img)
+    torch.cuda.synchronize()
+    img.copy_(torch.as_tensor((mu > 0).astype(np.float32), device=dev))
+    st0 = L.lmosem_get_stats(ctx.handle)
+
+    log(f"timing {args.steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.time()
+    e0.record(stream)
+    for _ in range(args.steps):
+        L.lmosem_iterate(ctx.handle, evs, 1, img)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - w0
+    ms_total = e0.elapsed_time(e1)
+    st1 = L.lmosem_get_stats(ctx.handle)
+    ms_step = ms_total / args.steps
+    value = J * args.steps / (ms_total * 1e-3)
+
+    # dominant kernel: forward projection, timed with HIP events on the same stream
+    log("timing kernels")
+    L.lmosem_set_timing(ctx.handle, True)
+    for _ in range(max(2, args.steps // 4)):
+        L.lmosem_iterate(ctx.handle, evs, 1, img)
+    ks = L.lmosem_get_stats(ctx.handle)
+    L.lmosem_set_timing(ctx.handle, False)
+    n_it = max(2, args.steps // 4)
+    useful_per_iter = (st1["useful_terms"] - st0["useful_terms"]) / args.steps
+    computed_per_iter = (st1["inner_terms"] - st0["inner_terms"]) / args.steps
+    launches = ks["forward_launches"]
+    fwd_s = ks["forward_ms"] * 1e-3 / launches
+    useful_per_launch = useful_per_iter * n_it / launches
+    achieved_terms = useful_per_launch / fwd_s
+    peak_terms = mix_peak_terms_per_s()
+    rates = L.lmosem_measure_alu_rates(stream)
+    roof = {
+        "bound": "alu",
+        "kernel": "k_forward (forward projection)",
+        "achieved": achieved_terms * FLOPS_PER_TERM / 1e12,
+        "peak": peak_terms * FLOPS_PER_TERM / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved_terms / peak_terms,
+        "traffic": None,
+        "per_unit": "one inner term (event, emission pixel, path end with non-zero position "
+                    "response) = 2 FMA + 1 exp2 = 5 flops",
+        "units_per_launch": useful_per_launch,
+        "avg_launch_ms": fwd_s * 1e3,
+        "computed_terms_per_launch": computed_per_iter * n_it / launches,
+        "measured_rates_per_s": rates,
+        "backproject_avg_ms": ks["backproject_ms"] / max(1, ks["backproject_launches"]),
+        "mean_update_avg_ms": ks["update_ms"] / max(1, ks["update_launches"]),
+    }
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (Monte-Carlo list-mode events from analytic brain phantom)",
+        "config": {"workload": "brain64: 64x64 px of 0.4 cm, 128 bins x 120 angles, 200k events "
+                               "100-175 keV, 8 subsets, exact first-order scatter path",
+                   "events": J, "subsets": g["n_subsets"], "support_pixels": int((mu > 0).sum()),
+                   "event_tile": ks["event_tile"], "path": "exact FP32"},
+        "roofline": roof,
+        "one_time_ms": {"create_tables": t_create * 1e3, "event_ingest": t_load * 1e3},
+        "wall_s_timed": wall,
+        "skipped_events": ks["skipped_events"],
+    }
+    L.lmosem_events_free(evs)
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, act, mu, ev)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

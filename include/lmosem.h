@@ -1,0 +1,229 @@
+/*
+ * lmosem.h — C ABI of the MI355X (gfx950) list-mode OSEM reconstruction with
+ * attenuation and first-order scatter compensation for 2-D SPECT
+ * (Rahman, Laforest, Jha, ISBI 2020).
+ *
+ * The problem (Sec. 2.1): from list-mode events A_j = (detector angle,
+ * position, energy), an attenuation map mu from CT and the acquisition time T,
+ * estimate the activity f by maximising the list-mode likelihood (Eq. 1-3),
+ * where each event's density is a mixture over photon paths (Eq. 2) weighted
+ * by f at the path's start pixel times the path sensitivity s_eff (Eq. 4).
+ * The estimate is computed with ordered-subsets list-mode EM (Eq. 7-9):
+ * subsets by detector angle, each sub-iteration starting from the previous
+ * one's estimate.
+ *
+ * Paths: the primary path q -> detector and the first-order in-plane scatter
+ * paths q -> s -> detector through every pixel s with mu(s) > 0 (Sec. 2.2).
+ * Path weights: attenuation by exact line integrals through mu, Compton
+ * energy loss and Klein-Nishina angular weight at the scatter point,
+ * Compton-only energy scaling of mu after the scatter, an ideal parallel-hole
+ * collimator, a truncated Gaussian position response of FWHM fwhm_u_cm and a
+ * Gaussian energy response of FWHM fwhm_e_kev evaluated at each event's
+ * recorded energy.
+ *
+ * Conventions
+ *   image      float32, row-major [ny][nx], pixel (i, j) centred at
+ *              ((i - (nx-1)/2) pixel_cm, (j - (ny-1)/2) pixel_cm).  Activity is
+ *              estimated on the mu > 0 support (the emission set); outputs are
+ *              0 elsewhere and inputs are ignored there.
+ *   angle      theta_a = angle0_rad + 2 pi a / n_angles, a in [0, n_angles);
+ *              photons reach the detector travelling along (cos, sin) theta_a.
+ *   position   u_bin in [0, n_bins): u = (u_bin - n_bins/2) bin_cm along
+ *              the detector axis (-sin, cos) theta_a.
+ *   subsets    subset i = { a : a mod n_subsets == i }, visited i = 0, 1, ...
+ *
+ * Memory and streams
+ *   Every array argument is a device pointer owned by the caller (for
+ *   example a torch tensor's data_ptr()), except those named *_host.  The
+ *   library keeps no caller pointer beyond a call.  All work is enqueued on
+ *   the HIP stream given to lmosem_create; calls return once the work is
+ *   enqueued, except those that validate inputs or write host memory, which
+ *   synchronise that stream.  A context is not thread-safe; separate
+ *   contexts are independent.  The context owns its device tables and frees
+ *   them in lmosem_destroy.
+ *
+ * Errors
+ *   Every call returns a status and never throws.  LMOSEM_EINVAL and
+ *   LMOSEM_ERANGE leave the context usable.  LMOSEM_EDEVICE (a failed HIP
+ *   call) poisons it: later calls return LMOSEM_ESTATE.  lmosem_last_error
+ *   returns a message for the last failure.
+ */
+#ifndef LMOSEM_H
+#define LMOSEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMOSEM_ABI_VERSION 1u
+
+typedef enum {
+    LMOSEM_OK = 0,
+    LMOSEM_EINVAL = -1,   /* bad argument or configuration */
+    LMOSEM_ERANGE = -2,   /* input values outside their valid range */
+    LMOSEM_ENOMEM = -3,   /* device allocation failed or exceeds the context cap */
+    LMOSEM_EDEVICE = -4,  /* a HIP call failed; the context is poisoned */
+    LMOSEM_ESTATE = -5,   /* context poisoned by an earlier device error */
+    LMOSEM_ENOTSUP = -6   /* valid but not supported by this build */
+} lmosem_status;
+
+typedef struct lmosem_ctx lmosem_ctx;
+typedef struct lmosem_evset lmosem_evset;
+
+/* Geometry and physics of one acquisition (all units explicit). */
+typedef struct {
+    uint32_t abi_version;     /* must equal LMOSEM_ABI_VERSION */
+    int32_t nx, ny;           /* image grid */
+    double pixel_cm;          /* pixel pitch */
+    int32_t n_bins;           /* detector bins; detector length n_bins * bin_cm */
+    double bin_cm;
+    int32_t n_angles;         /* detector angles over 360 degrees */
+    double angle0_rad;
+    double e0_kev;            /* photopeak energy */
+    double fwhm_e_kev;        /* energy resolution (constant FWHM) */
+    double fwhm_u_cm;         /* intrinsic position resolution (FWHM) */
+    double win_lo_kev;        /* accepted energies [win_lo, win_hi]: photopeak */
+    double win_hi_kev;        /*   and scatter windows together */
+    int32_t n_subsets;        /* 1 .. n_angles */
+    int32_t scatter_model;    /* 0: primary paths only; 1: primary + first-order scatter */
+    double acq_time;          /* T (> 0) */
+} lmosem_config;
+
+/* List-mode events, structure of arrays, device pointers, n >= 0. */
+typedef struct {
+    int64_t n;
+    const int32_t *angle;     /* [n] detector angle index */
+    const float *u_bin;       /* [n] position in detector bins, [0, n_bins) */
+    const float *energy_kev;  /* [n] recorded energy, within [win_lo, win_hi] */
+} lmosem_events;
+
+/* Several independent realisations concatenated in one event array:
+ * realisation r holds events offsets[r] .. offsets[r+1]-1.  Host pointer,
+ * offsets[0] == 0, non-decreasing, offsets[n_real] == events.n. */
+typedef struct {
+    int32_t n_real;
+    const int64_t *offsets;
+} lmosem_batch;
+
+/* Per-context counters, filled by lmosem_get_stats. */
+typedef struct {
+    int64_t n_support;          /* pixels with mu > 0 (emission and scatter set) */
+    int64_t skipped_events;     /* events whose model mean was <= 1e-30, since create */
+    int64_t inner_terms;        /* (event, emission pixel, path end) terms evaluated by
+                                   the forward projection, since create */
+    int64_t useful_terms;       /* of those, terms with a non-zero position response */
+    double table_ms;            /* time of the table build in lmosem_create */
+    int64_t table_bytes;        /* device bytes held by the path tables */
+    int32_t event_tile;         /* events per forward-projection tile */
+    int32_t reserved;
+    /* kernel times from HIP events on the context's stream, recorded only
+       while timing is enabled (lmosem_set_timing) */
+    int64_t forward_launches;
+    double forward_ms;          /* summed over forward-projection launches */
+    int64_t backproject_launches;
+    double backproject_ms;
+    int64_t update_launches;    /* mean + update kernels of a sub-iteration */
+    double update_ms;
+} lmosem_stats;
+
+/* Version of this ABI (LMOSEM_ABI_VERSION of the built library). */
+uint32_t lmosem_abi_version(void);
+
+/* Build a context for one attenuation map: validates the configuration and
+ * mu (finite, >= 0, at least one pixel > 0; mu is read on the device and
+ * copied once to the host), computes every path's weight and end energy
+ * (attenuation line integrals, Klein-Nishina and Compton factors; the model
+ * of s_eff in Eq. 4) and the per-subset sensitivity images (the
+ * denominators of Eq. 6/7).  mu_dev: [ny][nx] float32 in 1/cm at e0_kev.
+ * hip_stream: a hipStream_t, or NULL for the null stream.
+ * Errors: EINVAL (config), ERANGE (mu), ENOMEM, EDEVICE. */
+lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void *hip_stream,
+                            lmosem_ctx **out);
+
+/* Free the context and everything it owns (NULL is a no-op). */
+void lmosem_destroy(lmosem_ctx *ctx);
+
+/* Message describing the last failure on this context ("" if none). */
+const char *lmosem_last_error(const lmosem_ctx *ctx);
+
+/* Sensitivity image T * sum_{paths P_q reaching the subset's angles} s_eff(P_q)
+ * (denominator of Eq. 7) into sens_dev [ny][nx]; subset -1 sums all angles
+ * (denominator of Eq. 6).  Errors: EINVAL (subset out of range). */
+lmosem_status lmosem_sensitivity(lmosem_ctx *ctx, int32_t subset, float *sens_dev);
+
+/* Per-event means for a given image: mean_j = sum_q f_q h(q; A_j), the
+ * denominator of Eq. 8 (the path mixture of Eq. 2 without the normaliser of
+ * Eq. 4, which cancels).  image_dev [ny][nx], event_mean_dev [ev->n], in the
+ * caller's event order.  Validates the events (synchronises).
+ * Errors: EINVAL, ERANGE (events out of range), ENOMEM. */
+lmosem_status lmosem_forward(lmosem_ctx *ctx, const lmosem_events *ev, const float *image_dev,
+                             float *event_mean_dev);
+
+/* Weighted backprojection b_q = sum_j h(q; A_j) w_j into image_dev [ny][nx]
+ * (with w_j = 1/mean_j this is the numerator of Eq. 7 divided by f_q).
+ * weights_dev [ev->n].  Validates the events (synchronises). */
+lmosem_status lmosem_backproject(lmosem_ctx *ctx, const lmosem_events *ev,
+                                 const float *weights_dev, float *image_dev);
+
+/* One sub-iteration of Eq. 7 for subset `subset`: every given event is
+ * taken as a member of that subset (the caller passes the events detected
+ * at the subset's angles).  image_dev [ny][nx] is updated in place:
+ * f_q <- f_q * (sum_j h(q; A_j) / mean_j) / sens_q^(subset); pixels with zero
+ * sensitivity keep their value and events with mean <= 1e-30 are skipped
+ * and counted.  event_mean_dev (nullable, [ev->n]) receives the means at the
+ * input image.  Membership is checked only when the environment variable
+ * LMOSEM_VALIDATE=1 (then the call synchronises).  Errors: EINVAL, ERANGE. */
+lmosem_status lmosem_subset_update(lmosem_ctx *ctx, int32_t subset, const lmosem_events *ev,
+                                   float *image_dev, float *event_mean_dev);
+
+/* Full OS-LM-MLEM (Eq. 7-9): n_iters global iterations over all subsets in
+ * order, for one realisation (batch NULL) or several independent ones.
+ * init_dev (nullable: 1 on the support) is [ny][nx], shared by all
+ * realisations; images_dev [n_real][ny][nx] receives the estimates.
+ * loglik_host (nullable) [n_real][n_iters] receives, per global iteration,
+ * sum_i (sum_{j in S_i} log mean_j - sum_q f_q sens_q^(i)) at the estimate
+ * each sub-iteration starts from (for one subset: Eq. 3 up to constants at
+ * the iteration's starting estimate).  Validates events and init
+ * (synchronises).  Errors: EINVAL, ERANGE, ENOMEM. */
+lmosem_status lmosem_reconstruct(lmosem_ctx *ctx, const lmosem_events *ev,
+                                 const lmosem_batch *batch, int32_t n_iters,
+                                 const float *init_dev, float *images_dev, double *loglik_host);
+
+/* Prepared event sets: validate once, sort by (subset, realisation, angle,
+ * position) and plan the forward-projection tiles, so that repeated
+ * iterations pay nothing for ingest.  The set keeps device copies and is
+ * tied to its context; free it before the context. */
+lmosem_status lmosem_events_load(lmosem_ctx *ctx, const lmosem_events *ev,
+                                 const lmosem_batch *batch, lmosem_evset **out);
+void lmosem_events_free(lmosem_evset *set);
+
+/* n_iters global iterations on a prepared set; images_dev [n_real][ny][nx]
+ * is the starting estimate on entry and the result on return (values
+ * outside the support are set to 0).  loglik_host as in lmosem_reconstruct
+ * (nullable; if given the call synchronises). */
+lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters,
+                             float *images_dev, double *loglik_host);
+
+/* Tuning: events per forward tile (8, 16 or 32; 0 restores the default). */
+lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
+
+/* Counters of this context (synchronises the context's stream). */
+lmosem_status lmosem_get_stats(const lmosem_ctx *ctx, lmosem_stats *out);
+
+/* Enable (1) or disable (0) per-kernel timing with HIP events around every
+ * sub-iteration kernel; enabling also clears the accumulated times. */
+lmosem_status lmosem_set_timing(lmosem_ctx *ctx, int32_t enable);
+
+/* Diagnostic: measured vector-ALU rates of this GPU, in lane-operations per
+ * second: out[0] FP32 FMA, out[1] FP32 exp2 (v_exp_f32), out[2] the mix of
+ * two FMAs and one exp2 that the forward projection issues per term (in
+ * terms per second).  Runs short probe kernels on hip_stream (synchronises). */
+lmosem_status lmosem_measure_alu_rates(void *hip_stream, double *out3);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMOSEM_H */

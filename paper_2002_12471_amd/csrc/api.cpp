@@ -1,0 +1,547 @@
+// Host runtime and C ABI of the gfx950 list-mode OSEM library (include/lmosem.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lmosem_int.h"
+
+using namespace lmo;
+
+struct lmosem_ctx {
+    lmosem_config cfg{};
+    Geo g{};
+    Tables t{};
+    hipStream_t st = nullptr;
+    std::string err;
+    bool poisoned = false;
+    int ev_tile = 16;
+    int *bad_dev = nullptr;
+    unsigned long long *skipped_dev = nullptr;
+    int64_t terms = 0, useful = 0;
+    double table_ms = 0.0;
+    int64_t table_bytes = 0;
+    // per-kernel timing (HIP events around each launch while enabled)
+    bool timing = false;
+    struct Pending { hipEvent_t a, b; int kind; };
+    std::vector<Pending> pending;
+    int64_t launches[3] = {0, 0, 0};
+    double ms[3] = {0.0, 0.0, 0.0};
+};
+
+// Workspace of one prepared event set.
+struct lmosem_evset {
+    EvSet s;
+    float *H = nullptr;       // [max_rows][n_qpad]
+    float *pmean = nullptr;   // [n_groups][max_rows]
+    float *mean = nullptr;    // [max_rows]
+    float *inv = nullptr;     // [max_rows]
+    float *pb = nullptr;      // [max_chunks][n_qpad]
+    float *f = nullptr;       // [n_real][n_qpad]
+    double *ll = nullptr;     // [n_real]
+};
+
+namespace {
+
+lmosem_status set_err(lmosem_ctx *c, lmosem_status s, const std::string &msg) {
+    if (c) {
+        c->err = msg;
+        if (s == LMOSEM_EDEVICE) c->poisoned = true;
+    }
+    return s;
+}
+
+lmosem_status dev_err(lmosem_ctx *c, const char *what, hipError_t e) {
+    return set_err(c, LMOSEM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+lmosem_status alloc_err(lmosem_ctx *c, const char *what, hipError_t e) {
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return set_err(c, LMOSEM_ENOMEM, std::string(what) + ": out of device memory");
+    }
+    return dev_err(c, what, e);
+}
+
+// Closed form of the circle mean of the Klein-Nishina shape
+// Psi(c) = t^-3 + t^-1 - (1 - c^2) t^-2, t = 1 + k (1 - c), c = cos(phi):
+// with a = 1 + k, b = k, r = sqrt(a^2 - b^2),
+//   int t^-1 = 2 pi / r,  int t^-3 = pi (2 a^2 + b^2) / r^5,
+//   int sin^2 t^-2 = (a int t^-1 - 2 pi) / b^2.
+double psi_bar_closed(double k) {
+    double a = 1.0 + k, b = k, r = sqrt(a * a - b * b);
+    double j1 = 2.0 * M_PI / r;
+    double j3 = M_PI * (2.0 * a * a + b * b) / pow(r, 5.0);
+    double s2 = (a * j1 - 2.0 * M_PI) / (b * b);
+    return (j3 + j1 - s2) / (2.0 * M_PI);
+}
+
+double kn_total_host(double e) {
+    double k = e / kMeC2;
+    double l = log1p(2.0 * k);
+    double k1 = 1.0 + k, k2 = 1.0 + 2.0 * k;
+    return 2.0 * M_PI * (k1 / (k * k) * (2.0 * k1 / k2 - l / k) + l / (2.0 * k) - (1.0 + 3.0 * k) / (k2 * k2));
+}
+
+bool check_cfg(const lmosem_config *c, std::string &why) {
+    if (c->abi_version != LMOSEM_ABI_VERSION) { why = "abi_version mismatch"; return false; }
+    if (c->nx <= 0 || c->ny <= 0 || c->nx > 4096 || c->ny > 4096) { why = "bad grid size"; return false; }
+    if (!(c->pixel_cm > 0) || !(c->bin_cm > 0)) { why = "pixel_cm and bin_cm must be > 0"; return false; }
+    if (c->n_bins <= 0 || c->n_angles <= 0 || c->n_angles > 65535) { why = "bad detector size"; return false; }
+    if (!(c->e0_kev > 0) || !(c->fwhm_e_kev > 0) || !(c->fwhm_u_cm > 0)) {
+        why = "e0_kev and the FWHMs must be > 0";
+        return false;
+    }
+    if (!(c->win_lo_kev < c->win_hi_kev) || !(c->win_lo_kev > 0)) { why = "need 0 < win_lo < win_hi"; return false; }
+    if (c->n_subsets < 1 || c->n_subsets > c->n_angles) { why = "need 1 <= n_subsets <= n_angles"; return false; }
+    if (c->scatter_model != 0 && c->scatter_model != 1) {
+        why = "scatter_model must be 0 (primary) or 1 (first-order scatter)";
+        return false;
+    }
+    if (!(c->acq_time > 0)) { why = "acq_time must be > 0"; return false; }
+    return true;
+}
+
+bool check_events(lmosem_ctx *c, const lmosem_events *ev, lmosem_status &st) {
+    if (!ev || ev->n < 0 || ev->n > 0x7fffffffLL ||
+        (ev->n > 0 && (!ev->angle || !ev->u_bin || !ev->energy_kev))) {
+        st = set_err(c, LMOSEM_EINVAL, "bad event arrays");
+        return false;
+    }
+    int64_t bad = 0;
+    hipError_t e = validate_events(c->g, *ev, &bad, c->bad_dev, c->st);
+    if (e != hipSuccess) { st = dev_err(c, "validate events", e); return false; }
+    if (bad) {
+        st = set_err(c, LMOSEM_ERANGE, std::to_string(bad) + " events outside angle/position/energy range");
+        return false;
+    }
+    return true;
+}
+
+void free_set(lmosem_evset *s) {
+    if (!s) return;
+    hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
+    hipFree(s->s.crange); hipFree(s->s.rrange);
+    hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
+    hipFree(s->ll);
+    delete s;
+}
+
+lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch, int force_subset,
+                       lmosem_evset **out) {
+    lmosem_status st = LMOSEM_OK;
+    if (!check_events(c, ev, st)) return st;
+    std::vector<int64_t> offs;
+    if (batch) {
+        if (batch->n_real < 1 || !batch->offsets) return set_err(c, LMOSEM_EINVAL, "bad batch");
+        offs.assign(batch->offsets, batch->offsets + batch->n_real + 1);
+        if (offs[0] != 0 || offs.back() != ev->n) return set_err(c, LMOSEM_EINVAL, "batch offsets must span the events");
+        for (int r = 0; r < batch->n_real; ++r)
+            if (offs[r + 1] < offs[r]) return set_err(c, LMOSEM_EINVAL, "batch offsets must not decrease");
+    } else {
+        offs = {0, ev->n};
+    }
+    auto *s = new lmosem_evset();
+    s->s.ctx = c;
+    s->s.ev_tile = c->ev_tile;
+    std::string why;
+    hipError_t e = sort_events(c->g, c->t, *ev, offs, force_subset, s->s, c->st, why);
+    if (e != hipSuccess) {
+        free_set(s);
+        return e == hipErrorOutOfMemory ? set_err(c, LMOSEM_ENOMEM, why) : set_err(c, LMOSEM_EDEVICE, why);
+    }
+    const Geo &g = c->g;
+    size_t rows = std::max(s->s.max_rows, 1), groups = (g.n_qpad + 255) / 256;
+    size_t chunks = std::max(s->s.max_chunks, 1);
+#define AL(p, bytes) do { e = hipMalloc(&(p), (bytes)); if (e != hipSuccess) { free_set(s); return alloc_err(c, "workspace", e); } } while (0)
+    AL(s->H, sizeof(float) * rows * g.n_qpad);
+    AL(s->pmean, sizeof(float) * rows * groups);
+    AL(s->mean, sizeof(float) * rows);
+    AL(s->inv, sizeof(float) * rows);
+    AL(s->pb, sizeof(float) * chunks * g.n_qpad);
+    AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
+    AL(s->ll, sizeof(double) * s->s.n_real);
+#undef AL
+    *out = s;
+    return LMOSEM_OK;
+}
+
+// Run one launch, bracketed by HIP events on the context stream when timing
+// is enabled (kind 0 forward, 1 backprojection, 2 mean/update).
+template <class F>
+hipError_t timed(lmosem_ctx *c, int kind, F &&launch) {
+    if (!c->timing) return launch();
+    lmosem_ctx::Pending p{nullptr, nullptr, kind};
+    hipError_t e;
+    if ((e = hipEventCreate(&p.a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&p.b)) != hipSuccess) { hipEventDestroy(p.a); return e; }
+    if ((e = hipEventRecord(p.a, c->st)) == hipSuccess && (e = launch()) == hipSuccess)
+        e = hipEventRecord(p.b, c->st);
+    if (e != hipSuccess) { hipEventDestroy(p.a); hipEventDestroy(p.b); return e; }
+    c->pending.push_back(p);
+    return hipSuccess;
+}
+
+hipError_t drain_timing(lmosem_ctx *c) {
+    hipError_t e = hipSuccess;
+    for (auto &p : c->pending) {
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventSynchronize(p.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        c->ms[p.kind] += ms;
+        c->launches[p.kind] += 1;
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    c->pending.clear();
+    return e;
+}
+
+// One sub-iteration of Eq. 7 on all realisations of a prepared set.
+hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll) {
+    const Geo &g = c->g;
+    const EvSet &v = s->s;
+    const int rows = v.row_off[i + 1] - v.row_off[i];
+    const int n_tiles = v.tile_off[i + 1] - v.tile_off[i];
+    const int n_chunks = v.chunk_off[i + 1] - v.chunk_off[i];
+    const int groups = (g.n_qpad + 255) / 256;
+    const float *sens = c->t.sens + (size_t)i * g.n_qpad;
+    const int *crange = v.crange + (size_t)i * (v.n_real + 1);
+    const int *rrange = v.rrange + (size_t)i * (v.n_real + 1);
+    hipError_t e;
+    if (n_tiles > 0 &&
+        (e = timed(c, 0, [&] {
+             return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], n_tiles, v.u, v.e, s->f, s->H,
+                                   s->pmean, v.row_off[i], rows, c->st);
+         })) != hipSuccess)
+        return e;
+    if (rows > 0 &&
+        (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, c->st); })) !=
+            hipSuccess)
+        return e;
+    if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, c->st)) != hipSuccess)
+        return e;
+    if (n_chunks > 0 &&
+        (e = timed(c, 1, [&] {
+             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, s->H, s->inv, s->pb, c->st);
+         })) != hipSuccess)
+        return e;
+    if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, c->st); })) != hipSuccess)
+        return e;
+    c->terms += v.terms_sub[i];
+    c->useful += v.useful_sub[i];
+    return hipSuccess;
+}
+
+lmosem_status iterate_set(lmosem_ctx *c, lmosem_evset *s, int n_iters, double *ll_host) {
+    const Geo &g = c->g;
+    std::vector<double> ll;
+    if (ll_host) ll.assign((size_t)s->s.n_real * n_iters, 0.0);
+    std::vector<double> tmp(s->s.n_real);
+    hipError_t e;
+    for (int it = 0; it < n_iters; ++it) {
+        if (ll_host && (e = launch_fill_d(s->ll, s->s.n_real, 0.0, c->st)) != hipSuccess)
+            return dev_err(c, "clear loglik", e);
+        for (int i = 0; i < g.n_subsets; ++i)
+            if ((e = subiteration(c, s, i, ll_host != nullptr)) != hipSuccess) return dev_err(c, "sub-iteration", e);
+        if (ll_host) {
+            if ((e = hipMemcpyAsync(tmp.data(), s->ll, sizeof(double) * s->s.n_real, hipMemcpyDeviceToHost,
+                                    c->st)) != hipSuccess ||
+                (e = hipStreamSynchronize(c->st)) != hipSuccess)
+                return dev_err(c, "loglik", e);
+            for (int r = 0; r < s->s.n_real; ++r) ll[(size_t)r * n_iters + it] = tmp[r];
+        }
+    }
+    if (ll_host) std::copy(ll.begin(), ll.end(), ll_host);
+    return LMOSEM_OK;
+}
+
+#define GUARD(c)                                                              \
+    do {                                                                      \
+        if (!(c)) return LMOSEM_EINVAL;                                       \
+        if ((c)->poisoned) return LMOSEM_ESTATE;                              \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+uint32_t lmosem_abi_version(void) { return LMOSEM_ABI_VERSION; }
+
+const char *lmosem_last_error(const lmosem_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void *hip_stream, lmosem_ctx **out) {
+    if (!cfg || !mu_dev || !out) return LMOSEM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!check_cfg(cfg, why)) return LMOSEM_EINVAL;
+    auto *c = new lmosem_ctx();
+    c->cfg = *cfg;
+    c->st = (hipStream_t)hip_stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const int n_pix = cfg->nx * cfg->ny;
+    std::vector<float> mu(n_pix);
+    hipError_t e = hipMemcpyAsync(mu.data(), mu_dev, sizeof(float) * n_pix, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) { delete c; return LMOSEM_EDEVICE; }
+    std::vector<int> p_pix, q_of_pix(n_pix, -1);
+    for (int p = 0; p < n_pix; ++p) {
+        if (!(mu[p] >= 0.0f) || !std::isfinite(mu[p])) { delete c; return LMOSEM_ERANGE; }
+        if (mu[p] > 0.0f) { q_of_pix[p] = (int)p_pix.size(); p_pix.push_back(p); }
+    }
+    if (p_pix.empty()) { delete c; return LMOSEM_ERANGE; }
+
+    Geo &g = c->g;
+    g.nx = cfg->nx; g.ny = cfg->ny; g.n_pix = n_pix;
+    g.n_p = (int)p_pix.size();
+    g.n_qpad = (g.n_p + 63) / 64 * 64;
+    g.n_angles = cfg->n_angles; g.n_bins = cfg->n_bins; g.n_subsets = cfg->n_subsets;
+    g.scatter = cfg->scatter_model;
+    g.dx = cfg->pixel_cm; g.bin_cm = cfg->bin_cm; g.half_len = 0.5 * cfg->n_bins * cfg->bin_cm;
+    g.e0 = cfg->e0_kev; g.kappa = cfg->e0_kev / kMeC2;
+    const double fw = 2.0 * sqrt(2.0 * log(2.0));
+    g.sig_e = cfg->fwhm_e_kev / fw;
+    g.sig_u = cfg->fwhm_u_cm / fw;
+    g.win_lo = cfg->win_lo_kev; g.win_hi = cfg->win_hi_kev;
+    g.psi_bar = psi_bar_closed(g.kappa);
+    g.sigma_kn_e0 = kn_total_host(g.e0);
+    g.zk = g.sig_u * sqrt(2.0 * M_PI) * erf(3.0 / sqrt(2.0)) - 6.0 * g.sig_u * exp(-4.5);
+    g.e_c = std::round(0.5 * (g.win_lo + g.win_hi) * 64.0) / 64.0;
+    g.c2 = 1.0 / (2.0 * g.sig_e * g.sig_e * log(2.0));
+    g.acq_time = cfg->acq_time;
+
+    std::vector<double> cs(2 * g.n_angles);
+    for (int a = 0; a < g.n_angles; ++a) {
+        double th = cfg->angle0_rad + 2.0 * M_PI * a / g.n_angles;
+        cs[2 * a] = cos(th);
+        cs[2 * a + 1] = sin(th);
+    }
+#define CK(call, what) do { e = (call); if (e != hipSuccess) { lmosem_destroy(c); return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE; } } while (0)
+    CK(hipMalloc(&c->t.p_pix, sizeof(int) * (g.n_p + n_pix)), "alloc");
+    CK(hipMalloc(&c->t.mu, sizeof(float) * n_pix), "alloc");
+    CK(hipMalloc(&c->t.cs, sizeof(double) * 2 * g.n_angles), "alloc");
+    CK(hipMalloc(&c->bad_dev, sizeof(int)), "alloc");
+    CK(hipMalloc(&c->skipped_dev, sizeof(unsigned long long)), "alloc");
+    CK(hipMemsetAsync(c->skipped_dev, 0, sizeof(unsigned long long), c->st), "clear");
+    CK(hipMemcpyAsync(c->t.p_pix, p_pix.data(), sizeof(int) * g.n_p, hipMemcpyHostToDevice, c->st), "upload");
+    CK(hipMemcpyAsync(c->t.p_pix + g.n_p, q_of_pix.data(), sizeof(int) * n_pix, hipMemcpyHostToDevice, c->st),
+       "upload");
+    CK(hipMemcpyAsync(c->t.mu, mu.data(), sizeof(float) * n_pix, hipMemcpyHostToDevice, c->st), "upload");
+    CK(hipMemcpyAsync(c->t.cs, cs.data(), sizeof(double) * 2 * g.n_angles, hipMemcpyHostToDevice, c->st), "upload");
+#undef CK
+    std::string err;
+    e = build_tables(g, c->t, c->st, err, c->table_bytes);
+    if (e != hipSuccess) {
+        lmosem_destroy(c);
+        return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE;
+    }
+    c->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (const char *v = getenv("LMOSEM_EVENT_TILE")) {
+        int t = atoi(v);
+        if (t == 8 || t == 16 || t == 32) c->ev_tile = t;
+    }
+    *out = c;
+    return LMOSEM_OK;
+}
+
+void lmosem_destroy(lmosem_ctx *c) {
+    if (!c) return;
+    drain_timing(c);
+    hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted);
+    hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->bad_dev); hipFree(c->skipped_dev);
+    delete c;
+}
+
+lmosem_status lmosem_sensitivity(lmosem_ctx *c, int32_t subset, float *sens_dev) {
+    GUARD(c);
+    if (!sens_dev || subset < -1 || subset >= c->g.n_subsets) return set_err(c, LMOSEM_EINVAL, "bad subset");
+    const float *src = subset < 0 ? c->t.sens_all : c->t.sens + (size_t)subset * c->g.n_qpad;
+    hipError_t e = launch_scatter_image(c->g, c->t, src, 1, sens_dev, c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "sensitivity", e);
+}
+
+lmosem_status lmosem_events_load(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch,
+                                 lmosem_evset **out) {
+    GUARD(c);
+    if (!out) return set_err(c, LMOSEM_EINVAL, "null output");
+    *out = nullptr;
+    return load_set(c, ev, batch, -1, out);
+}
+
+void lmosem_events_free(lmosem_evset *s) { free_set(s); }
+
+lmosem_status lmosem_iterate(lmosem_ctx *c, lmosem_evset *s, int32_t n_iters, float *images_dev,
+                             double *loglik_host) {
+    GUARD(c);
+    if (!s || s->s.ctx != c || !images_dev || n_iters < 0) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    const Geo &g = c->g;
+    hipError_t e = launch_gather_image(g, c->t, images_dev, s->s.n_real, g.n_pix, s->f, 0, c->st);
+    if (e != hipSuccess) return dev_err(c, "gather image", e);
+    lmosem_status st = iterate_set(c, s, n_iters, loglik_host);
+    if (st != LMOSEM_OK) return st;
+    e = launch_scatter_image(g, c->t, s->f, s->s.n_real, images_dev, c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "scatter image", e);
+}
+
+lmosem_status lmosem_reconstruct(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch,
+                                 int32_t n_iters, const float *init_dev, float *images_dev,
+                                 double *loglik_host) {
+    GUARD(c);
+    if (!images_dev || n_iters < 0) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    const Geo &g = c->g;
+    hipError_t e;
+    if (init_dev) {
+        int bad = 0;
+        if ((e = hipMemsetAsync(c->bad_dev, 0, sizeof(int), c->st)) != hipSuccess ||
+            (e = launch_check_image(g, c->t, init_dev, c->bad_dev, c->st)) != hipSuccess ||
+            (e = hipMemcpyAsync(&bad, c->bad_dev, sizeof(int), hipMemcpyDeviceToHost, c->st)) != hipSuccess ||
+            (e = hipStreamSynchronize(c->st)) != hipSuccess)
+            return dev_err(c, "check init", e);
+        if (bad) return set_err(c, LMOSEM_ERANGE, "initial image negative or not finite on the support");
+    }
+    lmosem_evset *s = nullptr;
+    lmosem_status st = load_set(c, ev, batch, -1, &s);
+    if (st != LMOSEM_OK) return st;
+    e = launch_gather_image(g, c->t, init_dev, s->s.n_real, 0, s->f, 1, c->st);
+    if (e != hipSuccess) { free_set(s); return dev_err(c, "init", e); }
+    st = iterate_set(c, s, n_iters, loglik_host);
+    if (st == LMOSEM_OK) {
+        e = launch_scatter_image(g, c->t, s->f, s->s.n_real, images_dev, c->st);
+        if (e != hipSuccess) st = dev_err(c, "scatter image", e);
+    }
+    if (st == LMOSEM_OK && (e = hipStreamSynchronize(c->st)) != hipSuccess) st = dev_err(c, "reconstruct", e);
+    free_set(s);
+    return st;
+}
+
+lmosem_status lmosem_subset_update(lmosem_ctx *c, int32_t subset, const lmosem_events *ev, float *image_dev,
+                                   float *event_mean_dev) {
+    GUARD(c);
+    if (!image_dev || subset < 0 || subset >= c->g.n_subsets) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    const char *val = getenv("LMOSEM_VALIDATE");
+    if (val && atoi(val) == 1 && ev && ev->n > 0) {
+        std::vector<int32_t> ang(ev->n);
+        hipError_t e = hipMemcpyAsync(ang.data(), ev->angle, sizeof(int32_t) * ev->n, hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) return dev_err(c, "validate", e);
+        int64_t wrong = 0;
+        for (int32_t a : ang) wrong += (a >= 0 && a % c->g.n_subsets != subset);
+        if (wrong) return set_err(c, LMOSEM_ERANGE, std::to_string(wrong) + " events not in the subset");
+    }
+    lmosem_evset *s = nullptr;
+    lmosem_status st = load_set(c, ev, nullptr, subset, &s);
+    if (st != LMOSEM_OK) return st;
+    const Geo &g = c->g;
+    hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
+    if (e == hipSuccess) e = subiteration(c, s, subset, false);
+    if (e == hipSuccess && event_mean_dev)
+        e = launch_scatter_rows(s->mean, s->s.orig + s->s.row_off[subset],
+                                s->s.row_off[subset + 1] - s->s.row_off[subset], event_mean_dev, c->st);
+    if (e == hipSuccess) e = launch_scatter_image(g, c->t, s->f, 1, image_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    free_set(s);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "subset update", e);
+}
+
+lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float *image_dev, float *mean_dev) {
+    GUARD(c);
+    if (!image_dev || !mean_dev) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    lmosem_evset *s = nullptr;
+    lmosem_status st = load_set(c, ev, nullptr, 0, &s);
+    if (st != LMOSEM_OK) return st;
+    const Geo &g = c->g;
+    const EvSet &v = s->s;
+    const int rows = v.row_off[1];
+    hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
+    if (e == hipSuccess)
+        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, s->f, s->H, s->pmean, 0, rows, c->st);
+    if (e == hipSuccess)
+        e = launch_mean(s->pmean, (g.n_qpad + 255) / 256, rows, s->mean, s->inv, c->skipped_dev, c->st);
+    if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) { c->terms += v.terms_sub[0]; c->useful += v.useful_sub[0]; }
+    free_set(s);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "forward", e);
+}
+
+lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const float *weights_dev,
+                                 float *image_dev) {
+    GUARD(c);
+    if (!image_dev || (!weights_dev && ev && ev->n > 0)) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    lmosem_evset *s = nullptr;
+    lmosem_status st = load_set(c, ev, nullptr, 0, &s);
+    if (st != LMOSEM_OK) return st;
+    const Geo &g = c->g;
+    const EvSet &v = s->s;
+    const int rows = v.row_off[1];
+    hipError_t e = launch_fill(s->f, (size_t)g.n_qpad, 0.0f, c->st);
+    if (e == hipSuccess)
+        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, s->f, s->H, s->pmean, 0, rows, c->st);
+    if (e == hipSuccess) e = launch_gather_rows(weights_dev, v.orig, rows, s->inv, c->st);
+    if (e == hipSuccess) e = launch_backproject(g, v.chunks, v.chunk_off[1], s->H, s->inv, s->pb, c->st);
+    if (e == hipSuccess) e = launch_sum_real(g, v.crange, 1, s->pb, s->f, c->st);
+    if (e == hipSuccess) e = launch_scatter_image(g, c->t, s->f, 1, image_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) { c->terms += v.terms_sub[0]; c->useful += v.useful_sub[0]; }
+    free_set(s);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "backproject", e);
+}
+
+lmosem_status lmosem_set_tuning(lmosem_ctx *c, int32_t event_tile) {
+    GUARD(c);
+    if (event_tile == 0) event_tile = 16;
+    if (event_tile != 8 && event_tile != 16 && event_tile != 32)
+        return set_err(c, LMOSEM_EINVAL, "event_tile must be 8, 16 or 32");
+    c->ev_tile = event_tile;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_get_stats(const lmosem_ctx *c, lmosem_stats *out) {
+    if (!c || !out) return LMOSEM_EINVAL;
+    if (c->poisoned) return LMOSEM_ESTATE;
+    unsigned long long sk = 0;
+    hipError_t e = hipMemcpyAsync(&sk, c->skipped_dev, sizeof sk, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = drain_timing(const_cast<lmosem_ctx *>(c));
+    if (e != hipSuccess) return LMOSEM_EDEVICE;
+    out->n_support = c->g.n_p;
+    out->skipped_events = (int64_t)sk;
+    out->inner_terms = c->terms;
+    out->useful_terms = c->useful;
+    out->table_ms = c->table_ms;
+    out->table_bytes = c->table_bytes;
+    out->event_tile = c->ev_tile;
+    out->reserved = 0;
+    out->forward_launches = c->launches[0];
+    out->forward_ms = c->ms[0];
+    out->backproject_launches = c->launches[1];
+    out->backproject_ms = c->ms[1];
+    out->update_launches = c->launches[2];
+    out->update_ms = c->ms[2];
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_set_timing(lmosem_ctx *c, int32_t enable) {
+    GUARD(c);
+    hipError_t e = drain_timing(c);
+    if (e != hipSuccess) return dev_err(c, "timing", e);
+    c->timing = enable != 0;
+    if (c->timing) {
+        for (int k = 0; k < 3; ++k) { c->launches[k] = 0; c->ms[k] = 0.0; }
+    }
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_measure_alu_rates(void *hip_stream, double *out3) {
+    if (!out3) return LMOSEM_EINVAL;
+    hipError_t e = measure_alu_rates((hipStream_t)hip_stream, out3);
+    return e == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+}
+
+}  // extern "C"

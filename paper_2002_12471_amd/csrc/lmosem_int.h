@@ -1,0 +1,128 @@
+// Internal declarations of the gfx950 list-mode OSEM library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lmosem.h"
+
+namespace lmo {
+
+constexpr double kMeC2 = 510.99895;     // electron rest energy, keV
+constexpr float kNegHuge = -1.0e30f;     // log2 weight of a path that never contributes
+
+// Geometry and physics constants shared by the kernels (host-computed, FP64).
+struct Geo {
+    int nx, ny, n_pix;
+    int n_p;          // support pixels (emission = scatter = path-end set)
+    int n_qpad;       // n_p rounded up to a multiple of 64 (row stride of tables)
+    int n_angles, n_bins, n_subsets, scatter;
+    double dx, bin_cm, half_len;
+    double e0, kappa, sig_e, sig_u, win_lo, win_hi;
+    double psi_bar;       // circle mean of the Klein-Nishina shape at e0
+    double sigma_kn_e0;   // Klein-Nishina total cross-section at e0 (units r_e^2)
+    double zk;            // normaliser of the truncated position response
+    double e_c;           // energy centre for the table encoding
+    double c2;            // log2(e) / (2 sig_e^2)
+    double acq_time;
+};
+
+// One forward-projection tile: up to EV consecutive events of one
+// (subset, realisation, angle) group sorted by detector position, and the
+// rank range of path ends (sorted by detector position at that angle) whose
+// position response can reach any of them.
+struct Tile {
+    int e0;      // first event (index into the sorted event arrays)
+    int n;       // events in the tile
+    int angle;
+    int real;    // realisation
+    int r0, r1;  // path-end rank range [r0, r1)
+};
+
+// Backprojection chunk: rows [j0, j1) of one realisation within a sub-iteration.
+struct Chunk {
+    int j0, j1;  // rows relative to the sub-iteration's first row
+    int real;
+    int pad;
+};
+
+// Device tables of one context.
+struct Tables {
+    int *p_pix = nullptr;        // [n_p] support pixel index
+    float *mu = nullptr;         // [n_pix]
+    double *cs = nullptr;        // [n_angles][2] cos, sin of theta_a
+    int *s_sorted = nullptr;     // [n_angles][n_p] path-end support index by rank
+    double *us_sorted = nullptr; // [n_angles][n_p] detector position of each rank (cm)
+    float2 *T = nullptr;         // [n_angles][n_p][n_qpad] (alpha, beta) per path
+    float *sens = nullptr;       // [n_subsets][n_qpad]
+    float *sens_all = nullptr;   // [n_qpad]
+};
+
+// ---- table build (tables.hip) ----
+hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes);
+
+// ---- event ingest (events.hip) ----
+struct EvSet;
+hipError_t validate_events(const Geo &g, const lmosem_events &ev, int64_t *bad_host, int *bad_dev,
+                           hipStream_t st);
+hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
+                       const std::vector<int64_t> &offs, int force_subset, EvSet &set,
+                       hipStream_t st, std::string &err);
+
+// ---- per sub-iteration kernels (osem.hip) ----
+hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
+                          const float *ev_u, const float *ev_e, const float *f, float *H,
+                          float *pmean, int row_base, int n_rows, hipStream_t st);
+hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean, float *inv,
+                       unsigned long long *skipped, hipStream_t st);
+hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
+                              const float *inv, float *pb, hipStream_t st);
+hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
+                         const float *sens, float *f, hipStream_t st);
+hipError_t launch_loglik(const Geo &g, const int *rrange, int n_real, const float *mean,
+                         const float *f, const float *sens, double *ll, hipStream_t st);
+hipError_t launch_sum_real(const Geo &g, const int *crange, int n_real, const float *pb,
+                           float *out, hipStream_t st);
+hipError_t launch_gather_image(const Geo &g, const Tables &t, const float *img, int n_real,
+                               int64_t img_stride, float *f, int ones_if_null, hipStream_t st);
+hipError_t launch_scatter_image(const Geo &g, const Tables &t, const float *f, int n_real,
+                                float *img, hipStream_t st);
+hipError_t launch_scatter_rows(const float *src, const int *orig, int n, float *dst,
+                               hipStream_t st);
+hipError_t launch_gather_rows(const float *src, const int *orig, int n, float *dst,
+                              hipStream_t st);
+hipError_t launch_fill(float *p, size_t n, float v, hipStream_t st);
+hipError_t launch_fill_d(double *p, size_t n, double v, hipStream_t st);
+hipError_t launch_check_image(const Geo &g, const Tables &t, const float *img, int *bad,
+                              hipStream_t st);
+
+// ---- ALU rate probes (probe.hip) ----
+hipError_t measure_alu_rates(hipStream_t st, double *out3);
+
+// A prepared, sorted event set.
+struct EvSet {
+    lmosem_ctx *ctx = nullptr;
+    int n_real = 0;
+    int64_t n = 0;
+    int ev_tile = 16;
+    // sorted SoA
+    float *u = nullptr;      // detector position, cm
+    float *e = nullptr;      // energy minus the encoding centre, keV
+    int *orig = nullptr;     // original event index
+    // per subset
+    std::vector<int> row_off;               // [n_subsets+1] rows of each subset
+    std::vector<int> tile_off;              // [n_subsets+1]
+    std::vector<int> chunk_off;             // [n_subsets+1]
+    Tile *tiles = nullptr;                  // all tiles, subset-major
+    Chunk *chunks = nullptr;                // all chunks, subset-major
+    int *crange = nullptr;                  // [n_subsets][n_real+1] chunk ranges per realisation
+    int *rrange = nullptr;                  // [n_subsets][n_real+1] row ranges per realisation
+    std::vector<int64_t> terms_sub;         // per subset: terms evaluated
+    std::vector<int64_t> useful_sub;        // per subset: terms with K > 0
+    int max_rows = 0, max_chunks = 0;
+};
+
+}  // namespace lmo

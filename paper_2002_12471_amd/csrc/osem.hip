@@ -1,0 +1,361 @@
+// Kernels of one OS-LM-MLEM sub-iteration (Eq. 7-8).
+//
+//   forward      h_j(q) = sum over paths from q of  w G(E_j; E') K(u_j - u_end)
+//                (the system row of event j), stored as a row of H, and the
+//                partial sums of f_q h_j(q) over each pixel group
+//   mean         mean_j = sum_q f_q h_j(q)  (denominator of Eq. 8)
+//   backproject  b_q = sum_j h_j(q) / mean_j over a chunk of rows, one
+//                column slice per thread: every output has one owner, so no
+//                atomics and a fixed summation order
+//   update       f_q <- f_q * b_q / sens_q  (Eq. 7)
+//
+// The forward kernel is the hot loop.  A workgroup owns one tile of up to EV
+// events of one angle, sorted by detector position, and 256 emission pixels
+// (one per lane).  For every path end in the tile's rank range it reads the
+// (alpha, beta) pair of each lane's path once and reuses it for all EV
+// events; per event the term is one FMA for the exponent, one exp2 and one
+// FMA into the accumulator.  The event factor
+//     K'_js = K(u_j - u_s) / Z_K * 2^(-c2 (E_j - e_c)^2)
+// is computed once per (event, path end) in FP64 into LDS and read back as
+// a broadcast.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lmosem_int.h"
+
+namespace lmo {
+
+constexpr int kRch = 128;   // path-end ranks staged in LDS per pass
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int EV>
+__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles,
+                                                 const float2 *__restrict__ T,
+                                                 const double *__restrict__ us_sorted,
+                                                 const float *__restrict__ su,
+                                                 const float *__restrict__ se,
+                                                 const float *__restrict__ f,
+                                                 float *__restrict__ H, float *__restrict__ pmean,
+                                                 int row_base, int n_rows) {
+    __shared__ __align__(16) float Ks[kRch * EV];
+    __shared__ float red[4 * EV];
+    const Tile tl = tiles[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int q = blockIdx.y * 256 + tid;
+    const bool wave_on = (int)(blockIdx.y * 256 + wave * 64) < g.n_qpad;
+
+    float et[EV], acc[EV];
+#pragma unroll
+    for (int e = 0; e < EV; ++e) {
+        et[e] = e < tl.n ? se[tl.e0 + e] : 0.0f;
+        acc[e] = 0.0f;
+    }
+    const float2 *Tq = T + (size_t)tl.angle * g.n_p * g.n_qpad + (wave_on ? q : 0);
+    const double *us = us_sorted + (size_t)tl.angle * g.n_p;
+    const double inv2s2 = 1.0 / (2.0 * g.sig_u * g.sig_u);
+    const double edge = exp(-4.5);
+    const double kscale = 1.0 / g.zk;
+
+    for (int rc = tl.r0; rc < tl.r1; rc += kRch) {
+        const int nr = min(kRch, tl.r1 - rc);
+        __syncthreads();
+        for (int idx = tid; idx < nr * EV; idx += 256) {
+            const int r = idx / EV, e = idx - r * EV;
+            float kv = 0.0f;
+            if (e < tl.n) {
+                const double d = ((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm - us[rc + r];
+                const double gk = exp(-d * d * inv2s2) - edge;
+                if (gk > 0.0) {
+                    const double x = (double)se[tl.e0 + e];
+                    kv = (float)(gk * kscale * exp2(-g.c2 * x * x));
+                }
+            }
+            Ks[idx] = kv;
+        }
+        __syncthreads();
+        if (wave_on) {
+#pragma unroll 2
+            for (int r = 0; r < nr; ++r) {
+                const float2 ab = Tq[(size_t)(rc + r) * g.n_qpad];
+                const float4 *kr = reinterpret_cast<const float4 *>(Ks + r * EV);
+#pragma unroll
+                for (int e4 = 0; e4 < EV / 4; ++e4) {
+                    const float4 k = kr[e4];
+                    acc[4 * e4 + 0] = fmaf(k.x, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 0], ab.x)), acc[4 * e4 + 0]);
+                    acc[4 * e4 + 1] = fmaf(k.y, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 1], ab.x)), acc[4 * e4 + 1]);
+                    acc[4 * e4 + 2] = fmaf(k.z, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 2], ab.x)), acc[4 * e4 + 2]);
+                    acc[4 * e4 + 3] = fmaf(k.w, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 3], ab.x)), acc[4 * e4 + 3]);
+                }
+            }
+        }
+    }
+
+    if (wave_on) {
+        float *Hq = H + (size_t)(tl.e0 - row_base) * g.n_qpad + q;
+#pragma unroll
+        for (int e = 0; e < EV; ++e)
+            if (e < tl.n) Hq[(size_t)e * g.n_qpad] = acc[e];
+    }
+    const float fq = (wave_on && q < g.n_p) ? f[(size_t)tl.real * g.n_qpad + q] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) {
+        const float v = wave_sum(fq * acc[e]);
+        if (lane == 0) red[wave * EV + e] = v;
+    }
+    __syncthreads();
+    if (tid < tl.n) {
+        const float s = (red[tid] + red[EV + tid]) + (red[2 * EV + tid] + red[3 * EV + tid]);
+        pmean[(size_t)blockIdx.y * n_rows + (tl.e0 - row_base) + tid] = s;
+    }
+}
+
+hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
+                          const float *ev_u, const float *ev_e, const float *f, float *H,
+                          float *pmean, int row_base, int n_rows, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    dim3 grid((unsigned)n_tiles, (unsigned)((g.n_qpad + 255) / 256));
+    switch (ev_tile) {
+    case 8:
+        hipLaunchKernelGGL(k_forward<8>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
+                           f, H, pmean, row_base, n_rows);
+        break;
+    case 32:
+        hipLaunchKernelGGL(k_forward<32>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
+                           f, H, pmean, row_base, n_rows);
+        break;
+    default:
+        hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
+                           f, H, pmean, row_base, n_rows);
+        break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_mean(const float *__restrict__ pmean, int n_groups, int n_rows,
+                       float *__restrict__ mean, float *__restrict__ inv,
+                       unsigned long long *__restrict__ skipped) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int dead = 0;
+    if (j < n_rows) {
+        float s = 0.0f;
+        for (int k = 0; k < n_groups; ++k) s += pmean[(size_t)k * n_rows + j];
+        mean[j] = s;
+        dead = !(s > 1e-30f);
+        inv[j] = dead ? 0.0f : 1.0f / s;
+    }
+    const unsigned long long m = __ballot(dead);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(skipped, (unsigned long long)__popcll(m));
+}
+
+hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean, float *inv,
+                       unsigned long long *skipped, hipStream_t st) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mean, dim3((n_rows + 255) / 256), dim3(256), 0, st, pmean, n_groups, n_rows,
+                       mean, inv, skipped);
+    return hipGetLastError();
+}
+
+// pb[c][q] = sum_{j in chunk c} H[j][q] inv[j]; four columns per thread.
+__global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restrict__ chunks,
+                                                     const float *__restrict__ H,
+                                                     const float *__restrict__ inv,
+                                                     float *__restrict__ pb) {
+    const Chunk c = chunks[blockIdx.y];
+    const int q4 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (q4 >= g.n_qpad) return;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float *Hp = H + (size_t)c.j0 * g.n_qpad + q4;
+#pragma unroll 8
+    for (int j = c.j0; j < c.j1; ++j) {
+        const float4 h = *reinterpret_cast<const float4 *>(Hp);
+        const float w = inv[j];
+        acc.x = fmaf(h.x, w, acc.x);
+        acc.y = fmaf(h.y, w, acc.y);
+        acc.z = fmaf(h.z, w, acc.z);
+        acc.w = fmaf(h.w, w, acc.w);
+        Hp += g.n_qpad;
+    }
+    *reinterpret_cast<float4 *>(pb + (size_t)blockIdx.y * g.n_qpad + q4) = acc;
+}
+
+hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
+                              const float *inv, float *pb, hipStream_t st) {
+    if (n_chunks <= 0) return hipSuccess;
+    dim3 grid((unsigned)((g.n_qpad / 4 + 255) / 256), (unsigned)n_chunks);
+    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, st, g, chunks, H, inv, pb);
+    return hipGetLastError();
+}
+
+// f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks.
+__global__ void k_update(Geo g, const int *__restrict__ crange, const float *__restrict__ pb,
+                         const float *__restrict__ sens, float *__restrict__ f) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q >= g.n_p) return;
+    float b = 0.0f;
+    for (int c = crange[r]; c < crange[r + 1]; ++c) b += pb[(size_t)c * g.n_qpad + q];
+    const float s = sens[q];
+    float *fp = f + (size_t)r * g.n_qpad + q;
+    if (s > 0.0f) *fp = (*fp * b) / s;
+}
+
+hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
+                         const float *sens, float *f, hipStream_t st) {
+    hipLaunchKernelGGL(k_update, dim3((g.n_p + 255) / 256, n_real), dim3(256), 0, st, g, crange, pb, sens,
+                       f);
+    return hipGetLastError();
+}
+
+// out[r][q] = sum over realisation r's chunks of pb[c][q]
+__global__ void k_sum_real(Geo g, const int *__restrict__ crange, const float *__restrict__ pb,
+                           float *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q >= g.n_qpad) return;
+    float b = 0.0f;
+    for (int c = crange[r]; c < crange[r + 1]; ++c) b += pb[(size_t)c * g.n_qpad + q];
+    out[(size_t)r * g.n_qpad + q] = q < g.n_p ? b : 0.0f;
+}
+
+hipError_t launch_sum_real(const Geo &g, const int *crange, int n_real, const float *pb, float *out,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_real, dim3((g.n_qpad + 255) / 256, n_real), dim3(256), 0, st, g, crange, pb,
+                       out);
+    return hipGetLastError();
+}
+
+// ll[r] += sum_{rows of r} log mean_j - sum_q f_q sens_q  (one block per realisation)
+__global__ __launch_bounds__(256) void k_loglik(Geo g, const int *__restrict__ rrange,
+                                                const float *__restrict__ mean,
+                                                const float *__restrict__ f,
+                                                const float *__restrict__ sens, double *__restrict__ ll) {
+    __shared__ double red[256];
+    const int r = blockIdx.x, tid = threadIdx.x;
+    double s = 0.0;
+    for (int j = rrange[r] + tid; j < rrange[r + 1]; j += 256) {
+        const float m = mean[j];
+        if (m > 1e-30f) s += log((double)m);
+    }
+    for (int q = tid; q < g.n_p; q += 256) s -= (double)f[(size_t)r * g.n_qpad + q] * (double)sens[q];
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) ll[r] += red[0];
+}
+
+hipError_t launch_loglik(const Geo &g, const int *rrange, int n_real, const float *mean, const float *f,
+                         const float *sens, double *ll, hipStream_t st) {
+    hipLaunchKernelGGL(k_loglik, dim3(n_real), dim3(256), 0, st, g, rrange, mean, f, sens, ll);
+    return hipGetLastError();
+}
+
+// compact activity f[r][q] from images [r][ny][nx] (stride 0: one shared image);
+// a null image means 1 on the support
+__global__ void k_gather_image(Geo g, const int *__restrict__ p_pix, const float *__restrict__ img,
+                               int64_t stride, float *__restrict__ f) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q >= g.n_qpad) return;
+    float v = 0.0f;
+    if (q < g.n_p) v = img ? img[(size_t)r * stride + p_pix[q]] : 1.0f;
+    f[(size_t)r * g.n_qpad + q] = v;
+}
+
+hipError_t launch_gather_image(const Geo &g, const Tables &t, const float *img, int n_real,
+                               int64_t img_stride, float *f, int, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_image, dim3((g.n_qpad + 255) / 256, n_real), dim3(256), 0, st, g, t.p_pix,
+                       img, img_stride, f);
+    return hipGetLastError();
+}
+
+// images [r][ny][nx] from compact f (0 off the support)
+__global__ void k_scatter_image(Geo g, const int *__restrict__ q_of_pix, const float *__restrict__ f,
+                                float *__restrict__ img) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (p >= g.n_pix) return;
+    const int q = q_of_pix[p];
+    img[(size_t)r * g.n_pix + p] = q >= 0 ? f[(size_t)r * g.n_qpad + q] : 0.0f;
+}
+
+// q_of_pix is stored right after p_pix in the same allocation
+hipError_t launch_scatter_image(const Geo &g, const Tables &t, const float *f, int n_real, float *img,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_image, dim3((g.n_pix + 255) / 256, n_real), dim3(256), 0, st, g,
+                       t.p_pix + g.n_p, f, img);
+    return hipGetLastError();
+}
+
+__global__ void k_scatter_rows(const float *__restrict__ src, const int *__restrict__ orig, int n,
+                               float *__restrict__ dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[orig[k]] = src[k];
+}
+
+hipError_t launch_scatter_rows(const float *src, const int *orig, int n, float *dst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_rows, dim3((n + 255) / 256), dim3(256), 0, st, src, orig, n, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_rows(const float *__restrict__ src, const int *__restrict__ orig, int n,
+                              float *__restrict__ dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[orig[k]];
+}
+
+hipError_t launch_gather_rows(const float *src, const int *orig, int n, float *dst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3((n + 255) / 256), dim3(256), 0, st, src, orig, n, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(float *__restrict__ p, size_t n, float v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(float *p, size_t n, float v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_d(double *__restrict__ p, size_t n, double v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_d(double *p, size_t n, double v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// count support pixels whose value is negative or not finite
+__global__ void k_check_image(Geo g, const int *__restrict__ p_pix, const float *__restrict__ img,
+                              int *__restrict__ bad) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 0;
+    if (q < g.n_p) {
+        const float v = img[p_pix[q]];
+        b = !(v >= 0.0f && v <= 3.4e38f);
+    }
+    const unsigned long long m = __ballot(b);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (int)__popcll(m));
+}
+
+hipError_t launch_check_image(const Geo &g, const Tables &t, const float *img, int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_image, dim3((g.n_p + 255) / 256), dim3(256), 0, st, g, t.p_pix, img, bad);
+    return hipGetLastError();
+}
+
+}  // namespace lmo

@@ -1,0 +1,242 @@
+// Path tables for one attenuation map (built once per context, FP64 on the GPU).
+//
+// Every path of the model starts at an emission pixel q and ends at a pixel
+// s where it leaves for the detector along n_a: s == q is the primary path,
+// s != q the first-order in-plane scatter path through s (Sec. 2.2).  For
+// each angle a the path ends are ranked by their detector position
+// u_s(a) = c_s . t_a, so that the ends an event's position response can reach
+// form one contiguous rank range.  Per (a, rank, q) the table stores the
+// path's weight and end energy encoded for the forward kernel:
+//     alpha = log2(w / (sqrt(2 pi) sig_e)) - c2 (E' - e_c)^2,  beta = 2 c2 (E' - e_c)
+// so that w G(E; E') = 2^(alpha + beta (E - e_c) - c2 (E - e_c)^2).
+// The per-subset sensitivity (the denominators of Eq. 6/7) is accumulated
+// from the same weights times the detector and window acceptances.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "lmosem_int.h"
+
+namespace lmo {
+
+// Exact radiological path from the centre of pixel (i, j) along (dirx, diry)
+// for a length tmax (or until the ray leaves the grid), by stepping from
+// boundary to boundary (Amanatides and Woo, Eurographics 1987).
+__device__ double traverse(const float *__restrict__ mu, int nx, int ny, double dx, int i, int j,
+                           double dirx, double diry, double tmax) {
+    const double inf = 1e300;
+    int sx = dirx > 0 ? 1 : (dirx < 0 ? -1 : 0);
+    int sy = diry > 0 ? 1 : (diry < 0 ? -1 : 0);
+    double tdx = sx ? dx / fabs(dirx) : inf;
+    double tdy = sy ? dx / fabs(diry) : inf;
+    double tmx = sx ? 0.5 * tdx : inf;
+    double tmy = sy ? 0.5 * tdy : inf;
+    double t = 0.0, sum = 0.0;
+    for (;;) {
+        double tn = fmin(fmin(tmx, tmy), tmax);
+        sum += (double)mu[j * nx + i] * (tn - t);
+        t = tn;
+        if (t >= tmax) break;
+        if (tmx <= tmy) {
+            i += sx;
+            tmx += tdx;
+        } else {
+            j += sy;
+            tmy += tdy;
+        }
+        if (i < 0 || i >= nx || j < 0 || j >= ny) break;
+    }
+    return sum;
+}
+
+// Klein-Nishina total cross-section in units of r_e^2.
+__device__ __host__ inline double kn_total(double e) {
+    double k = e / kMeC2;
+    double l = log1p(2.0 * k);
+    double k1 = 1.0 + k, k2 = 1.0 + 2.0 * k;
+    return 2.0 * M_PI * (k1 / (k * k) * (2.0 * k1 / k2 - l / k) + l / (2.0 * k) - (1.0 + 3.0 * k) / (k2 * k2));
+}
+
+// L_a(p): attenuation from the centre of support pixel p to the detector.
+__global__ void k_line_to_detector(Geo g, const float *__restrict__ mu, const int *__restrict__ p_pix,
+                                   const double *__restrict__ cs, double *__restrict__ L) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.n_angles * g.n_p) return;
+    int a = idx / g.n_p, p = idx % g.n_p;
+    int pix = p_pix[p];
+    L[idx] = traverse(mu, g.nx, g.ny, g.dx, pix % g.nx, pix / g.nx, cs[2 * a], cs[2 * a + 1], 1e300);
+}
+
+// Bt[s][q] = B(q, s) = mu(s) dx^2 exp(-l(q,s)) / (2 pi r): the probability that
+// a photon emitted at q interacts at the scatter point s (0 for s == q).
+__global__ void k_scatter_points(Geo g, const float *__restrict__ mu, const int *__restrict__ p_pix,
+                                 double *__restrict__ Bt) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = blockIdx.y;
+    if (q >= g.n_p) return;
+    double b = 0.0;
+    if (q != s) {
+        int pq = p_pix[q], ps = p_pix[s];
+        int di = ps % g.nx - pq % g.nx, dj = ps / g.nx - pq / g.nx;
+        double r = g.dx * sqrt((double)(di * di + dj * dj));
+        double ell = traverse(mu, g.nx, g.ny, g.dx, pq % g.nx, pq / g.nx, g.dx * di / r,
+                              g.dx * dj / r, r);
+        b = (double)mu[ps] * g.dx * g.dx * exp(-ell) / (2.0 * M_PI * r);
+    }
+    Bt[(size_t)s * g.n_p + q] = b;
+}
+
+__device__ inline double centre_x(const Geo &g, int pix) { return ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx; }
+__device__ inline double centre_y(const Geo &g, int pix) { return ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx; }
+
+// fraction of the truncated position response centred at up on the detector
+__device__ double detector_mass(const Geo &g, double up) {
+    double s = g.sig_u;
+    double a = fmax(-g.half_len - up, -3.0 * s), b = fmin(g.half_len - up, 3.0 * s);
+    if (b <= a) return 0.0;
+    double gs = s * sqrt(M_PI / 2.0) * (erf(b / (M_SQRT2 * s)) - erf(a / (M_SQRT2 * s)));
+    return (gs - exp(-4.5) * (b - a)) / g.zk;
+}
+
+// Rank path ends by detector position per angle (ties by index).
+__global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
+                       int *__restrict__ s_sorted, double *__restrict__ us_sorted, double *__restrict__ D_sorted) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (p >= g.n_p) return;
+    double tx = -cs[2 * a + 1], ty = cs[2 * a];
+    int pix = p_pix[p];
+    double u = centre_x(g, pix) * tx + centre_y(g, pix) * ty;
+    int rank = 0;
+    for (int k = 0; k < g.n_p; ++k) {
+        int pk = p_pix[k];
+        double uk = centre_x(g, pk) * tx + centre_y(g, pk) * ty;
+        rank += (uk < u) || (uk == u && k < p);
+    }
+    size_t o = (size_t)a * g.n_p + rank;
+    s_sorted[o] = p;
+    us_sorted[o] = u;
+    D_sorted[o] = detector_mass(g, u);
+}
+
+// Path table and per-angle sensitivities.  One thread per (angle, emission
+// pixel q); it walks the path ends in rank order.
+__global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
+                             const double *__restrict__ L, const double *__restrict__ Bt,
+                             const int *__restrict__ s_sorted, const double *__restrict__ D_sorted,
+                             float2 *__restrict__ T, double *__restrict__ sens_a) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (q >= g.n_qpad) return;
+    float2 *Ta = T + (size_t)a * g.n_p * g.n_qpad + q;
+    if (q >= g.n_p) {
+        for (int r = 0; r < g.n_p; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
+        sens_a[(size_t)a * g.n_qpad + q] = 0.0;
+        return;
+    }
+    const double nx = cs[2 * a], ny = cs[2 * a + 1];
+    const int pq = p_pix[q];
+    const int iq = pq % g.nx, jq = pq / g.nx;
+    const double log2_gnorm = -log2(sqrt(2.0 * M_PI) * g.sig_e);
+    const double s2 = M_SQRT2 * g.sig_e;
+    double sens = 0.0;
+    for (int r = 0; r < g.n_p; ++r) {
+        size_t o = (size_t)a * g.n_p + r;
+        int s = s_sorted[o];
+        double w, ep;
+        if (s == q) {
+            w = exp(-L[(size_t)a * g.n_p + q]);
+            ep = g.e0;
+        } else if (g.scatter) {
+            int ps = p_pix[s];
+            int di = ps % g.nx - iq, dj = ps / g.nx - jq;
+            double c = (di * nx + dj * ny) / sqrt((double)(di * di + dj * dj));
+            double t = 1.0 + g.kappa * (1.0 - c);
+            double P = 1.0 / t;
+            ep = g.e0 * P;
+            double psi = P * P * (P + t - 1.0 + c * c);
+            double rho = kn_total(ep) / g.sigma_kn_e0;
+            w = Bt[(size_t)s * g.n_p + q] * psi / g.psi_bar * exp(-rho * L[(size_t)a * g.n_p + s]);
+        } else {
+            w = 0.0;
+            ep = g.e0;
+        }
+        float alpha = kNegHuge, beta = 0.0f;
+        if (w > 0.0) {
+            double ec = ep - g.e_c;
+            alpha = (float)(log2(w) + log2_gnorm - g.c2 * ec * ec);
+            beta = (float)(2.0 * g.c2 * ec);
+            double win = 0.5 * (erf((g.win_hi - ep) / s2) - erf((g.win_lo - ep) / s2));
+            sens += w * D_sorted[o] * win;
+        }
+        Ta[(size_t)r * g.n_qpad] = make_float2(alpha, beta);
+    }
+    sens_a[(size_t)a * g.n_qpad + q] = sens;
+}
+
+// sens[i][q] = T sum_{a mod N_s == i} sens_a[a][q]; sens_all = sum over subsets.
+__global__ void k_sens_reduce(Geo g, const double *__restrict__ sens_a, float *__restrict__ sens,
+                              float *__restrict__ sens_all) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.n_qpad) return;
+    double tot = 0.0;
+    for (int i = 0; i < g.n_subsets; ++i) {
+        double s = 0.0;
+        for (int a = i; a < g.n_angles; a += g.n_subsets) s += sens_a[(size_t)a * g.n_qpad + q];
+        sens[(size_t)i * g.n_qpad + q] = (float)(g.acq_time * s);
+        tot += s;
+    }
+    sens_all[q] = (float)(g.acq_time * tot);
+}
+
+hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes) {
+    hipError_t e;
+    double *L = nullptr, *Bt = nullptr, *D_sorted = nullptr, *sens_a = nullptr;
+    size_t nT = (size_t)g.n_angles * g.n_p * g.n_qpad;
+    auto fail = [&](const char *what, hipError_t code) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(code));
+        err = buf;
+        hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a);
+        return code;
+    };
+#define CK(call, what) do { e = (call); if (e != hipSuccess) return fail(what, e); } while (0)
+    CK(hipMalloc(&L, sizeof(double) * g.n_angles * g.n_p), "alloc L");
+    CK(hipMalloc(&Bt, sizeof(double) * (size_t)g.n_p * g.n_p), "alloc B");
+    CK(hipMalloc(&D_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc D");
+    CK(hipMalloc(&sens_a, sizeof(double) * g.n_angles * g.n_qpad), "alloc sens_a");
+    CK(hipMalloc(&t.s_sorted, sizeof(int) * g.n_angles * g.n_p), "alloc ranks");
+    CK(hipMalloc(&t.us_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc positions");
+    CK(hipMalloc(&t.T, sizeof(float2) * nT), "alloc path table");
+    CK(hipMalloc(&t.sens, sizeof(float) * g.n_subsets * g.n_qpad), "alloc sens");
+    CK(hipMalloc(&t.sens_all, sizeof(float) * g.n_qpad), "alloc sens_all");
+    bytes = (int64_t)(sizeof(float2) * nT + sizeof(int) * g.n_angles * g.n_p +
+                      sizeof(double) * g.n_angles * g.n_p + sizeof(float) * (g.n_subsets + 1) * g.n_qpad);
+
+    int na_np = g.n_angles * g.n_p;
+    hipLaunchKernelGGL(k_line_to_detector, dim3((na_np + 255) / 256), dim3(256), 0, st, g, t.mu,
+                       t.p_pix, t.cs, L);
+    CK(hipGetLastError(), "line integrals");
+    if (g.scatter) {
+        hipLaunchKernelGGL(k_scatter_points, dim3((g.n_p + 255) / 256, g.n_p), dim3(256), 0, st, g,
+                           t.mu, t.p_pix, Bt);
+        CK(hipGetLastError(), "scatter points");
+    }
+    hipLaunchKernelGGL(k_rank, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix,
+                       t.cs, t.s_sorted, t.us_sorted, D_sorted);
+    CK(hipGetLastError(), "rank");
+    hipLaunchKernelGGL(k_path_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g,
+                       t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a);
+    CK(hipGetLastError(), "path table");
+    hipLaunchKernelGGL(k_sens_reduce, dim3((g.n_qpad + 255) / 256), dim3(256), 0, st, g, sens_a,
+                       t.sens, t.sens_all);
+    CK(hipGetLastError(), "sensitivity");
+    CK(hipStreamSynchronize(st), "table build");
+    hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a);
+#undef CK
+    return hipSuccess;
+}
+
+}  // namespace lmo
