@@ -126,7 +126,7 @@ bool check_events(lmosem_ctx *c, const lmosem_events *ev, lmosem_status &st) {
 
 void free_set(lmosem_evset *s) {
     if (!s) return;
-    hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
+    hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
     hipFree(s->ll);
@@ -217,8 +217,8 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll) {
     hipError_t e;
     if (n_tiles > 0 &&
         (e = timed(c, 0, [&] {
-             return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], n_tiles, v.u, v.e, s->f, s->H,
-                                   s->pmean, v.row_off[i], rows, c->st);
+             return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], n_tiles, v.u, v.e, v.efac, s->f,
+                                   s->H, s->pmean, v.row_off[i], rows, c->st);
          })) != hipSuccess)
         return e;
     if (rows > 0 &&
@@ -460,7 +460,8 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
     const int rows = v.row_off[1];
     hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
     if (e == hipSuccess)
-        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, s->f, s->H, s->pmean, 0, rows, c->st);
+        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, v.efac, s->f, s->H, s->pmean, 0,
+                           rows, c->st);
     if (e == hipSuccess)
         e = launch_mean(s->pmean, (g.n_qpad + 255) / 256, rows, s->mean, s->inv, c->skipped_dev, c->st);
     if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
@@ -482,7 +483,8 @@ lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const f
     const int rows = v.row_off[1];
     hipError_t e = launch_fill(s->f, (size_t)g.n_qpad, 0.0f, c->st);
     if (e == hipSuccess)
-        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, s->f, s->H, s->pmean, 0, rows, c->st);
+        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, v.efac, s->f, s->H, s->pmean, 0,
+                           rows, c->st);
     if (e == hipSuccess) e = launch_gather_rows(weights_dev, v.orig, rows, s->inv, c->st);
     if (e == hipSuccess) e = launch_backproject(g, v.chunks, v.chunk_off[1], s->H, s->inv, s->pb, c->st);
     if (e == hipSuccess) e = launch_sum_real(g, v.crange, 1, s->pb, s->f, c->st);

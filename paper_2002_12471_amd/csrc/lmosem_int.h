@@ -74,7 +74,7 @@ hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
 
 // ---- per sub-iteration kernels (osem.hip) ----
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
-                          const float *ev_u, const float *ev_e, const float *f, float *H,
+                          const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
                           float *pmean, int row_base, int n_rows, hipStream_t st);
 hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean, float *inv,
                        unsigned long long *skipped, hipStream_t st);
@@ -111,6 +111,7 @@ struct EvSet {
     // sorted SoA
     float *u = nullptr;      // detector position, cm
     float *e = nullptr;      // energy minus the encoding centre, keV
+    float *efac = nullptr;   // 2^(-c2 e^2) / Z_K per event
     int *orig = nullptr;     // original event index
     // per subset
     std::vector<int> row_off;               // [n_subsets+1] rows of each subset

@@ -16,8 +16,9 @@
 // events; per event the term is one FMA for the exponent, one exp2 and one
 // FMA into the accumulator.  The event factor
 //     K'_js = K(u_j - u_s) / Z_K * 2^(-c2 (E_j - e_c)^2)
-// is computed once per (event, path end) in FP64 into LDS and read back as
-// a broadcast.
+// is computed once per (event, path end) into LDS and read back as a
+// broadcast; the energy factor 2^(-c2 (E_j - e_c)^2) / Z_K is precomputed per
+// event at ingest.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -33,21 +34,36 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// Map the dispatch index to a logical (pixel group, tile) index so that each
+// XCD (workgroups are dealt to the 8 XCDs round-robin) runs one contiguous
+// run of logical indices: consecutive tiles of one angle and pixel group then
+// share that XCD's L2 copy of the path-table slice they all read.
+__device__ inline int xcd_logical(int p, int n) {
+    constexpr int kXcd = 8;
+    const int x = p % kXcd, k = p / kXcd;
+    const int m = n / kXcd, rem = n % kXcd;
+    return x * m + min(x, rem) + k;
+}
+
 template <int EV>
-__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles,
+__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles, int n_tiles,
                                                  const float2 *__restrict__ T,
                                                  const double *__restrict__ us_sorted,
                                                  const float *__restrict__ su,
                                                  const float *__restrict__ se,
+                                                 const float *__restrict__ efac,
                                                  const float *__restrict__ f,
                                                  float *__restrict__ H, float *__restrict__ pmean,
                                                  int row_base, int n_rows) {
     __shared__ __align__(16) float Ks[kRch * EV];
     __shared__ float red[4 * EV];
-    const Tile tl = tiles[blockIdx.x];
+    const int n_groups = (g.n_qpad + 255) / 256;
+    const int logical = xcd_logical(blockIdx.x, n_tiles * n_groups);
+    const int grp = logical / n_tiles;
+    const Tile tl = tiles[logical - grp * n_tiles];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int q = blockIdx.y * 256 + tid;
-    const bool wave_on = (int)(blockIdx.y * 256 + wave * 64) < g.n_qpad;
+    const int q = grp * 256 + tid;
+    const bool wave_on = grp * 256 + wave * 64 < g.n_qpad;
 
     float et[EV], acc[EV];
 #pragma unroll
@@ -57,9 +73,8 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
     }
     const float2 *Tq = T + (size_t)tl.angle * g.n_p * g.n_qpad + (wave_on ? q : 0);
     const double *us = us_sorted + (size_t)tl.angle * g.n_p;
-    const double inv2s2 = 1.0 / (2.0 * g.sig_u * g.sig_u);
-    const double edge = exp(-4.5);
-    const double kscale = 1.0 / g.zk;
+    const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
+    const float edge = expf(-4.5f);
 
     for (int rc = tl.r0; rc < tl.r1; rc += kRch) {
         const int nr = min(kRch, tl.r1 - rc);
@@ -68,20 +83,22 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
             const int r = idx / EV, e = idx - r * EV;
             float kv = 0.0f;
             if (e < tl.n) {
-                const double d = ((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm - us[rc + r];
-                const double gk = exp(-d * d * inv2s2) - edge;
-                if (gk > 0.0) {
-                    const double x = (double)se[tl.e0 + e];
-                    kv = (float)(gk * kscale * exp2(-g.c2 * x * x));
-                }
+                // offset in FP64 (both positions are O(10 cm)), response in FP32
+                const float d = (float)(((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm - us[rc + r]);
+                const float gk = __expf(-d * d * inv2s2) - edge;
+                kv = gk > 0.0f ? gk * efac[tl.e0 + e] : 0.0f;
             }
             Ks[idx] = kv;
         }
         __syncthreads();
         if (wave_on) {
-#pragma unroll 2
+            // two-deep software prefetch of this lane's path-table entries
+            float2 ab0 = Tq[(size_t)rc * g.n_qpad];
+            float2 ab1 = nr > 1 ? Tq[(size_t)(rc + 1) * g.n_qpad] : ab0;
             for (int r = 0; r < nr; ++r) {
-                const float2 ab = Tq[(size_t)(rc + r) * g.n_qpad];
+                const float2 ab = ab0;
+                ab0 = ab1;
+                if (r + 2 < nr) ab1 = Tq[(size_t)(rc + r + 2) * g.n_qpad];
                 const float4 *kr = reinterpret_cast<const float4 *>(Ks + r * EV);
 #pragma unroll
                 for (int e4 = 0; e4 < EV / 4; ++e4) {
@@ -110,27 +127,28 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
     __syncthreads();
     if (tid < tl.n) {
         const float s = (red[tid] + red[EV + tid]) + (red[2 * EV + tid] + red[3 * EV + tid]);
-        pmean[(size_t)blockIdx.y * n_rows + (tl.e0 - row_base) + tid] = s;
+        pmean[(size_t)grp * n_rows + (tl.e0 - row_base) + tid] = s;
     }
 }
 
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
-                          const float *ev_u, const float *ev_e, const float *f, float *H,
+                          const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
                           float *pmean, int row_base, int n_rows, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    dim3 grid((unsigned)n_tiles, (unsigned)((g.n_qpad + 255) / 256));
+    const int n_groups = (g.n_qpad + 255) / 256;
+    dim3 grid((unsigned)(n_tiles * n_groups));
     switch (ev_tile) {
     case 8:
-        hipLaunchKernelGGL(k_forward<8>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
-                           f, H, pmean, row_base, n_rows);
+        hipLaunchKernelGGL(k_forward<8>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
+                           ev_e, efac, f, H, pmean, row_base, n_rows);
         break;
     case 32:
-        hipLaunchKernelGGL(k_forward<32>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
-                           f, H, pmean, row_base, n_rows);
+        hipLaunchKernelGGL(k_forward<32>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
+                           ev_e, efac, f, H, pmean, row_base, n_rows);
         break;
     default:
-        hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, st, g, tiles, t.T, t.us_sorted, ev_u, ev_e,
-                           f, H, pmean, row_base, n_rows);
+        hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
+                           ev_e, efac, f, H, pmean, row_base, n_rows);
         break;
     }
     return hipGetLastError();
