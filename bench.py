@@ -42,6 +42,27 @@ def mix_peak_terms_per_s():
     return N_CU * CLK * FMA_LANES / cyc
 
 
+def profiled_traffic(event_tile):
+    """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if the kernel source or tile size changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_forward_brain64.md")
+    src = os.path.join(ROOT, "paper_2002_12471_amd", "csrc", "osem.hip")
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                fields[k.split(" (")[0].strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("source_sha256") != sha or int(fields.get("event_tile", -1)) != event_tile:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, act, mu, ev, n_sample=1024, seed=11):
     """The FP64 oracle on the host cores: one subset update (system rows,
     forward, backprojection, update) for a seeded sample of subset 0's events."""
@@ -170,7 +191,7 @@ def main():
         "peak": peak_terms * FLOPS_PER_TERM / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved_terms / peak_terms,
-        "traffic": None,
+        "traffic": profiled_traffic(ks["event_tile"]),
         "per_unit": "one inner term (event, emission pixel, path end with non-zero position "
                     "response) = 2 FMA + 1 exp2 = 5 flops",
         "units_per_launch": useful_per_launch,

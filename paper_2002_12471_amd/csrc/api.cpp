@@ -21,7 +21,7 @@ struct lmosem_ctx {
     hipStream_t st = nullptr;
     std::string err;
     bool poisoned = false;
-    int ev_tile = 16;
+    int ev_tile = 8;
     int *bad_dev = nullptr;
     unsigned long long *skipped_dev = nullptr;
     int64_t terms = 0, useful = 0;
@@ -157,7 +157,7 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
         return e == hipErrorOutOfMemory ? set_err(c, LMOSEM_ENOMEM, why) : set_err(c, LMOSEM_EDEVICE, why);
     }
     const Geo &g = c->g;
-    size_t rows = std::max(s->s.max_rows, 1), groups = (g.n_qpad + 255) / 256;
+    size_t rows = std::max(s->s.max_rows, 1), groups = forward_groups(g);
     size_t chunks = std::max(s->s.max_chunks, 1);
 #define AL(p, bytes) do { e = hipMalloc(&(p), (bytes)); if (e != hipSuccess) { free_set(s); return alloc_err(c, "workspace", e); } } while (0)
     AL(s->H, sizeof(float) * rows * g.n_qpad);
@@ -210,7 +210,7 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll) {
     const int rows = v.row_off[i + 1] - v.row_off[i];
     const int n_tiles = v.tile_off[i + 1] - v.tile_off[i];
     const int n_chunks = v.chunk_off[i + 1] - v.chunk_off[i];
-    const int groups = (g.n_qpad + 255) / 256;
+    const int groups = forward_groups(g);
     const float *sens = c->t.sens + (size_t)i * g.n_qpad;
     const int *crange = v.crange + (size_t)i * (v.n_real + 1);
     const int *rrange = v.rrange + (size_t)i * (v.n_real + 1);
@@ -463,7 +463,7 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
         e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, v.efac, s->f, s->H, s->pmean, 0,
                            rows, c->st);
     if (e == hipSuccess)
-        e = launch_mean(s->pmean, (g.n_qpad + 255) / 256, rows, s->mean, s->inv, c->skipped_dev, c->st);
+        e = launch_mean(s->pmean, forward_groups(g), rows, s->mean, s->inv, c->skipped_dev, c->st);
     if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e == hipSuccess) { c->terms += v.terms_sub[0]; c->useful += v.useful_sub[0]; }
@@ -497,7 +497,7 @@ lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const f
 
 lmosem_status lmosem_set_tuning(lmosem_ctx *c, int32_t event_tile) {
     GUARD(c);
-    if (event_tile == 0) event_tile = 16;
+    if (event_tile == 0) event_tile = 8;
     if (event_tile != 8 && event_tile != 16 && event_tile != 32)
         return set_err(c, LMOSEM_EINVAL, "event_tile must be 8, 16 or 32");
     c->ev_tile = event_tile;

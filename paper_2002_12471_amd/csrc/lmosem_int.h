@@ -73,6 +73,7 @@ hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
                        hipStream_t st, std::string &err);
 
 // ---- per sub-iteration kernels (osem.hip) ----
+int forward_groups(const Geo &g);
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
                           const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
                           float *pmean, int row_base, int n_rows, hipStream_t st);

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "lmosem_int.h"
 
 namespace lmo {
@@ -34,34 +36,16 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// Map the dispatch index to a logical (pixel group, tile) index so that each
-// XCD (workgroups are dealt to the 8 XCDs round-robin) runs one contiguous
-// run of logical indices: consecutive tiles of one angle and pixel group then
-// share that XCD's L2 copy of the path-table slice they all read.
-__device__ inline int xcd_logical(int p, int n) {
-    constexpr int kXcd = 8;
-    const int x = p % kXcd, k = p / kXcd;
-    const int m = n / kXcd, rem = n % kXcd;
-    return x * m + min(x, rem) + k;
-}
-
 template <int EV>
-__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles, int n_tiles,
-                                                 const float2 *__restrict__ T,
-                                                 const double *__restrict__ us_sorted,
-                                                 const float *__restrict__ su,
-                                                 const float *__restrict__ se,
-                                                 const float *__restrict__ efac,
-                                                 const float *__restrict__ f,
-                                                 float *__restrict__ H, float *__restrict__ pmean,
-                                                 int row_base, int n_rows) {
-    __shared__ __align__(16) float Ks[kRch * EV];
-    __shared__ float red[4 * EV];
-    const int n_groups = (g.n_qpad + 255) / 256;
-    const int logical = xcd_logical(blockIdx.x, n_tiles * n_groups);
+__device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restrict__ tiles, int n_tiles,
+                                             int logical, const float2 *__restrict__ T,
+                                             const double *__restrict__ us_sorted,
+                                             const float *__restrict__ su, const float *__restrict__ se,
+                                             const float *__restrict__ efac, const float *__restrict__ f,
+                                             float *__restrict__ H, float *__restrict__ pmean, int row_base,
+                                             int n_rows, float *Ks, float *red, int tid, int wave, int lane) {
     const int grp = logical / n_tiles;
     const Tile tl = tiles[logical - grp * n_tiles];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int q = grp * 256 + tid;
     const bool wave_on = grp * 256 + wave * 64 < g.n_qpad;
 
@@ -92,22 +76,31 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
         }
         __syncthreads();
         if (wave_on) {
-            // two-deep software prefetch of this lane's path-table entries
-            float2 ab0 = Tq[(size_t)rc * g.n_qpad];
-            float2 ab1 = nr > 1 ? Tq[(size_t)(rc + 1) * g.n_qpad] : ab0;
+            // two-deep software prefetch of this lane's path-table entries;
+            // the index is clamped so every load is unconditional
+            const float2 *Tr = Tq + (size_t)rc * g.n_qpad;
+            float2 ab_cur = Tr[0];
+            float2 ab_nxt = Tr[(size_t)min(1, nr - 1) * g.n_qpad];
             for (int r = 0; r < nr; ++r) {
-                const float2 ab = ab0;
-                ab0 = ab1;
-                if (r + 2 < nr) ab1 = Tq[(size_t)(rc + r + 2) * g.n_qpad];
+                const float2 ab_fut = Tr[(size_t)min(r + 2, nr - 1) * g.n_qpad];
                 const float4 *kr = reinterpret_cast<const float4 *>(Ks + r * EV);
+                float4 k4[EV / 4];
+#pragma unroll
+                for (int e4 = 0; e4 < EV / 4; ++e4) k4[e4] = kr[e4];
+                float x[EV];
+#pragma unroll
+                for (int e = 0; e < EV; ++e) x[e] = fmaf(ab_cur.y, et[e], ab_cur.x);
+#pragma unroll
+                for (int e = 0; e < EV; ++e) x[e] = __builtin_amdgcn_exp2f(x[e]);
 #pragma unroll
                 for (int e4 = 0; e4 < EV / 4; ++e4) {
-                    const float4 k = kr[e4];
-                    acc[4 * e4 + 0] = fmaf(k.x, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 0], ab.x)), acc[4 * e4 + 0]);
-                    acc[4 * e4 + 1] = fmaf(k.y, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 1], ab.x)), acc[4 * e4 + 1]);
-                    acc[4 * e4 + 2] = fmaf(k.z, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 2], ab.x)), acc[4 * e4 + 2]);
-                    acc[4 * e4 + 3] = fmaf(k.w, __builtin_amdgcn_exp2f(fmaf(ab.y, et[4 * e4 + 3], ab.x)), acc[4 * e4 + 3]);
+                    acc[4 * e4 + 0] = fmaf(k4[e4].x, x[4 * e4 + 0], acc[4 * e4 + 0]);
+                    acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
+                    acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
+                    acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
                 }
+                ab_cur = ab_nxt;
+                ab_nxt = ab_fut;
             }
         }
     }
@@ -131,27 +124,63 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
     }
 }
 
+// Map the dispatch index to a logical (pixel group, tile) item so that each
+// XCD (workgroups are dealt to the 8 XCDs round-robin) runs one contiguous run
+// of items: consecutive tiles of one angle and pixel group then share that
+// XCD's L2 copy of the path-table slice they read.  (A persistent kernel that
+// drained per-XCD work queues was measured slower than this hardware-
+// scheduled grid on this workload.)
+__device__ inline int xcd_logical(int p, int n) {
+    constexpr int kXcd = 8;
+    const int x = p % kXcd, k = p / kXcd;
+    const int m = n / kXcd, rem = n % kXcd;
+    return x * m + min(x, rem) + k;
+}
+
+template <int EV>
+__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles, int n_tiles,
+                                                 const float2 *__restrict__ T,
+                                                 const double *__restrict__ us_sorted,
+                                                 const float *__restrict__ su,
+                                                 const float *__restrict__ se,
+                                                 const float *__restrict__ efac,
+                                                 const float *__restrict__ f,
+                                                 float *__restrict__ H, float *__restrict__ pmean,
+                                                 int row_base, int n_rows) {
+    __shared__ __align__(16) float Ks[kRch * EV];
+    __shared__ float red[4 * EV];
+    const int n_groups = (g.n_qpad + 255) / 256;
+    const int logical = xcd_logical(blockIdx.x, n_tiles * n_groups);
+    const int tid = threadIdx.x;
+    forward_item<EV>(g, tiles, n_tiles, logical, T, us_sorted, su, se, efac, f, H, pmean, row_base, n_rows, Ks,
+                     red, tid, tid >> 6, tid & 63);
+}
+
+// pixel groups of the forward launch (one group per 256 pixels)
+int forward_groups(const Geo &g) { return (g.n_qpad + 255) / 256; }
+
+template <int EV>
+static hipError_t launch_ev(const Geo &g, const Tables &t, const Tile *tiles, int n_tiles, const float *ev_u,
+                            const float *ev_e, const float *efac, const float *f, float *H, float *pmean,
+                            int row_base, int n_rows, hipStream_t st) {
+    const int n_work = n_tiles * forward_groups(g);
+    hipLaunchKernelGGL(k_forward<EV>, dim3(n_work), dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
+                       ev_e, efac, f, H, pmean, row_base, n_rows);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
                           const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
                           float *pmean, int row_base, int n_rows, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    const int n_groups = (g.n_qpad + 255) / 256;
-    dim3 grid((unsigned)(n_tiles * n_groups));
     switch (ev_tile) {
-    case 8:
-        hipLaunchKernelGGL(k_forward<8>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
-                           ev_e, efac, f, H, pmean, row_base, n_rows);
-        break;
+    case 16:
+        return launch_ev<16>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
     case 32:
-        hipLaunchKernelGGL(k_forward<32>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
-                           ev_e, efac, f, H, pmean, row_base, n_rows);
-        break;
+        return launch_ev<32>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
     default:
-        hipLaunchKernelGGL(k_forward<16>, grid, dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
-                           ev_e, efac, f, H, pmean, row_base, n_rows);
-        break;
+        return launch_ev<8>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
     }
-    return hipGetLastError();
 }
 
 __global__ void k_mean(const float *__restrict__ pmean, int n_groups, int n_rows,
