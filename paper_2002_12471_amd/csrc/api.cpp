@@ -301,6 +301,7 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     g.nx = cfg->nx; g.ny = cfg->ny; g.n_pix = n_pix;
     g.n_p = (int)p_pix.size();
     g.n_qpad = (g.n_p + 63) / 64 * 64;
+    g.n_rpad = g.n_p + kRankPad;
     g.n_angles = cfg->n_angles; g.n_bins = cfg->n_bins; g.n_subsets = cfg->n_subsets;
     g.scatter = cfg->scatter_model;
     g.dx = cfg->pixel_cm; g.bin_cm = cfg->bin_cm; g.half_len = 0.5 * cfg->n_bins * cfg->bin_cm;

@@ -13,12 +13,14 @@ namespace lmo {
 
 constexpr double kMeC2 = 510.99895;     // electron rest energy, keV
 constexpr float kNegHuge = -1.0e30f;     // log2 weight of a path that never contributes
+constexpr int kRankPad = 8;              // padding rank rows per angle (never contribute)
 
 // Geometry and physics constants shared by the kernels (host-computed, FP64).
 struct Geo {
     int nx, ny, n_pix;
     int n_p;          // support pixels (emission = scatter = path-end set)
     int n_qpad;       // n_p rounded up to a multiple of 64 (row stride of tables)
+    int n_rpad;       // rank rows per angle in the path table: n_p + kRankPad
     int n_angles, n_bins, n_subsets, scatter;
     double dx, bin_cm, half_len;
     double e0, kappa, sig_e, sig_u, win_lo, win_hi;
@@ -56,7 +58,7 @@ struct Tables {
     double *cs = nullptr;        // [n_angles][2] cos, sin of theta_a
     int *s_sorted = nullptr;     // [n_angles][n_p] path-end support index by rank
     double *us_sorted = nullptr; // [n_angles][n_p] detector position of each rank (cm)
-    float2 *T = nullptr;         // [n_angles][n_p][n_qpad] (alpha, beta) per path
+    float2 *T = nullptr;         // [n_angles][n_rpad][n_qpad] (alpha, beta) per path
     float *sens = nullptr;       // [n_subsets][n_qpad]
     float *sens_all = nullptr;   // [n_qpad]
 };

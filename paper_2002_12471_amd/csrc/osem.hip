@@ -55,18 +55,23 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         et[e] = e < tl.n ? se[tl.e0 + e] : 0.0f;
         acc[e] = 0.0f;
     }
-    const float2 *Tq = T + (size_t)tl.angle * g.n_p * g.n_qpad + (wave_on ? q : 0);
+    // table slice of this angle: uniform base (SGPRs) plus a 32-bit per-lane
+    // offset, so the loads use the scalar-base addressing form
+    const char *Tbase = reinterpret_cast<const char *>(T + (size_t)tl.angle * g.n_rpad * g.n_qpad);
+    const uint32_t lane_off = (uint32_t)(wave_on ? q : 0) * (uint32_t)sizeof(float2);
+    const size_t rstride = (size_t)g.n_qpad * sizeof(float2);
     const double *us = us_sorted + (size_t)tl.angle * g.n_p;
     const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
     const float edge = expf(-4.5f);
 
     for (int rc = tl.r0; rc < tl.r1; rc += kRch) {
         const int nr = min(kRch, tl.r1 - rc);
+        const int nr4 = (nr + 3) & ~3;      // ranks are processed in groups of 4
         __syncthreads();
-        for (int idx = tid; idx < nr * EV; idx += 256) {
+        for (int idx = tid; idx < nr4 * EV; idx += 256) {
             const int r = idx / EV, e = idx - r * EV;
             float kv = 0.0f;
-            if (e < tl.n) {
+            if (e < tl.n && r < nr) {
                 // offset in FP64 (both positions are O(10 cm)), response in FP32
                 const float d = (float)(((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm - us[rc + r]);
                 const float gk = __expf(-d * d * inv2s2) - edge;
@@ -76,31 +81,43 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         }
         __syncthreads();
         if (wave_on) {
-            // two-deep software prefetch of this lane's path-table entries;
-            // the index is clamped so every load is unconditional
-            const float2 *Tr = Tq + (size_t)rc * g.n_qpad;
-            float2 ab_cur = Tr[0];
-            float2 ab_nxt = Tr[(size_t)min(1, nr - 1) * g.n_qpad];
-            for (int r = 0; r < nr; ++r) {
-                const float2 ab_fut = Tr[(size_t)min(r + 2, nr - 1) * g.n_qpad];
-                const float4 *kr = reinterpret_cast<const float4 *>(Ks + r * EV);
-                float4 k4[EV / 4];
+            // groups of 4 ranks; the next group's table entries are loaded
+            // while this one is computed.  Ranks past the tile (up to 7) read
+            // the padding rows of the table and meet K' = 0.
+            const int n_grp = __builtin_amdgcn_readfirstlane(nr4 >> 2);
+            const char *Tg = Tbase + (size_t)rc * rstride;
+            float2 cur[4];
 #pragma unroll
-                for (int e4 = 0; e4 < EV / 4; ++e4) k4[e4] = kr[e4];
-                float x[EV];
+            for (int i = 0; i < 4; ++i)
+                cur[i] = *reinterpret_cast<const float2 *>(Tg + i * rstride + lane_off);
+            for (int gi = 0; gi < n_grp; ++gi) {
+                size_t nxt_off = (size_t)(gi + 1) * 4 * rstride;
+                asm volatile("" : "+s"(nxt_off));   // keep the prefetch where it is
+                float2 nxt[4];
 #pragma unroll
-                for (int e = 0; e < EV; ++e) x[e] = fmaf(ab_cur.y, et[e], ab_cur.x);
+                for (int i = 0; i < 4; ++i)
+                    nxt[i] = *reinterpret_cast<const float2 *>(Tg + nxt_off + i * rstride + lane_off);
 #pragma unroll
-                for (int e = 0; e < EV; ++e) x[e] = __builtin_amdgcn_exp2f(x[e]);
+                for (int i = 0; i < 4; ++i) {
+                    const float4 *kr = reinterpret_cast<const float4 *>(Ks + (gi * 4 + i) * EV);
+                    float4 k4[EV / 4];
 #pragma unroll
-                for (int e4 = 0; e4 < EV / 4; ++e4) {
-                    acc[4 * e4 + 0] = fmaf(k4[e4].x, x[4 * e4 + 0], acc[4 * e4 + 0]);
-                    acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
-                    acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
-                    acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
+                    for (int e4 = 0; e4 < EV / 4; ++e4) k4[e4] = kr[e4];
+                    float x[EV];
+#pragma unroll
+                    for (int e = 0; e < EV; ++e) x[e] = fmaf(cur[i].y, et[e], cur[i].x);
+#pragma unroll
+                    for (int e = 0; e < EV; ++e) x[e] = __builtin_amdgcn_exp2f(x[e]);
+#pragma unroll
+                    for (int e4 = 0; e4 < EV / 4; ++e4) {
+                        acc[4 * e4 + 0] = fmaf(k4[e4].x, x[4 * e4 + 0], acc[4 * e4 + 0]);
+                        acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
+                        acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
+                        acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
+                    }
                 }
-                ab_cur = ab_nxt;
-                ab_nxt = ab_fut;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
             }
         }
     }

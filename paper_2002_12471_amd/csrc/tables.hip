@@ -130,7 +130,8 @@ __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double 
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int a = blockIdx.y;
     if (q >= g.n_qpad) return;
-    float2 *Ta = T + (size_t)a * g.n_p * g.n_qpad + q;
+    float2 *Ta = T + (size_t)a * g.n_rpad * g.n_qpad + q;
+    for (int r = g.n_p; r < g.n_rpad; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
     if (q >= g.n_p) {
         for (int r = 0; r < g.n_p; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
         sens_a[(size_t)a * g.n_qpad + q] = 0.0;
@@ -194,7 +195,7 @@ __global__ void k_sens_reduce(Geo g, const double *__restrict__ sens_a, float *_
 hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes) {
     hipError_t e;
     double *L = nullptr, *Bt = nullptr, *D_sorted = nullptr, *sens_a = nullptr;
-    size_t nT = (size_t)g.n_angles * g.n_p * g.n_qpad;
+    size_t nT = (size_t)g.n_angles * g.n_rpad * g.n_qpad;
     auto fail = [&](const char *what, hipError_t code) {
         char buf[256];
         snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(code));
