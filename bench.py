@@ -1,15 +1,20 @@
 """Benchmark: list-mode events/s per OSEM subset update on one MI355X.
 
-Workload (brain64): 64x64 pixels of 0.4 cm, skull ring (mu 0.25/cm) around
-brain (mu 0.15/cm, activity 1) with caudate/putamen ellipses at 8:1 uptake,
-128 detector bins of 0.2 cm x 120 angles over 360 degrees, 200k list-mode
-events over 100-175 keV from the Monte-Carlo acquisition, 8 subsets.
+Default workload (brain64): 64x64 pixels of 0.4 cm, skull ring (mu 0.25/cm)
+around brain (mu 0.15/cm, activity 1) with caudate/putamen ellipses at 8:1
+uptake, 128 detector bins of 0.2 cm x 120 angles over 360 degrees, 200k
+list-mode events over 100-175 keV from the Monte-Carlo acquisition, 8
+subsets.  --workload batch_tiny runs 64 realisations of the 16x16 disk with
+log-uniform 50k-500k events each in one batch; --workload brain128 runs the
+same head at 128x128 pixels of 0.2 cm with 2M events per realisation over
+90-175 keV and 16 subsets.
 
-One step is one global OS-LM-MLEM iteration: the 8 subset updates (forward
+One step is one global OS-LM-MLEM iteration: every subset update (forward
 projection, per-event means, backprojection, multiplicative update) over all
-events, inputs resident in HBM.  value = events per second = J / step time
-(the sum over subsets of J_i over the sum of t_i).  Table build, event
-ingest and the CPU baseline are timed outside the timed region.
+events of all realisations, inputs resident in HBM.  value = events per
+second = events / step time (the sum over subsets of J_i over the sum of
+t_i).  Table build, event ingest, autotuning and the CPU baseline are timed
+outside the timed region.
 """
 from __future__ import annotations
 
@@ -32,6 +37,17 @@ FMA_LANES, TRANS_LANES = 64, 32
 FLOPS_PER_TERM = 5      # FMA (2) + exp2 (1) + FMA (2)
 
 
+WORKLOAD_TEXT = {
+    "tiny": "tiny: 16x16 disk of 0.8 cm px, 16 bins x 16 angles, 5000 events 100-175 keV, 1 subset",
+    "brain64": "brain64: 64x64 px of 0.4 cm, 128 bins x 120 angles, 200k events 100-175 keV, "
+               "8 subsets, exact first-order scatter path",
+    "batch_tiny": "batch_tiny: 64 realisations of the 16x16 disk (0.8 cm px, 16 bins x 16 angles), "
+                  "50k-500k events each (log-uniform), 1 subset, one launch per kernel for all",
+    "brain128": "brain128: 128x128 px of 0.2 cm, 256 bins x 120 angles, 2M events per realisation "
+                "90-175 keV, 16 subsets, exact first-order scatter path",
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -42,7 +58,7 @@ def mix_peak_terms_per_s():
     return N_CU * CLK * FMA_LANES / cyc
 
 
-def profiled_traffic(event_tile):
+def profiled_traffic(event_tile, workload):
     """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None if the kernel source or tile size changed
     since the counters were taken."""
@@ -56,7 +72,8 @@ def profiled_traffic(event_tile):
                 k, v = line.split(":", 1)
                 fields[k.split(" (")[0].strip()] = v.strip()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if fields.get("source_sha256") != sha or int(fields.get("event_tile", -1)) != event_tile:
+        if (workload != "brain64" or fields.get("source_sha256") != sha
+                or int(fields.get("event_tile", -1)) != event_tile):
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -69,6 +86,8 @@ def cpu_baseline(w, act, mu, ev, n_sample=1024, seed=11):
     import numpy as np
     import oracle as O
     g = w.geom.as_dict()
+    if w.name == "brain128":
+        n_sample = min(n_sample, 256)
     t0 = time.time()
     m = O.OracleModel(g, mu)
     t_model = time.time() - t0
@@ -82,7 +101,7 @@ def cpu_baseline(w, act, mu, ev, n_sample=1024, seed=11):
     O.subset_update(H, f, sens)
     dt = time.time() - t0
     return {"value": len(idx) / dt, "unit": "events/s", "cores": m.n_threads, "kind": "oracle",
-            "sample": f"{len(idx)} seeded events of subset 0 of brain64: FP64 system rows, "
+            "sample": f"{len(idx)} seeded events of subset 0 of {w.name}: FP64 system rows, "
                       f"forward, backprojection and update ({dt:.1f} s wall on {m.n_threads} "
                       f"threads; model build {t_model:.1f} s not counted)"}
 
@@ -94,6 +113,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--event-tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="brain64", choices=["brain64", "tiny", "batch_tiny", "brain128"])
+    ap.add_argument("--realisations", type=int, default=0,
+                    help="realisations for the batched workloads (default: 64 for batch_tiny, 2 for brain128)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -113,12 +135,26 @@ def main():
     from paper_2002_12471_amd import lmosem as L
 
     dev = torch.device("cuda:0")
-    w = synth.workload("brain64")
+    w = synth.workload(args.workload)
     g = w.geom.as_dict()
     act, mu = synth.phantom(w)
-    log("generating events")
-    ev = synth.workload_events(w)
+    log(f"generating events ({args.workload})")
+    offsets = None
+    if args.workload in ("brain64", "tiny"):
+        ev = synth.workload_events(w)
+    else:
+        if args.workload == "batch_tiny":
+            n_real = args.realisations or w.n_real
+            sizes = synth.batch_event_counts(w)[:n_real]
+        else:
+            n_real = args.realisations or 2
+            sizes = np.full(n_real, w.n_events)
+        parts = [synth.workload_events(w, realisation=r, n_events=int(n)) for r, n in enumerate(sizes)]
+        ev = {k: np.concatenate([p[k] for p in parts]) for k in ("angle", "u_bin", "energy")}
+        offsets = [0] + list(np.cumsum(sizes).astype(int))
+        del parts
     J = len(ev["angle"])
+    n_real = 1 if offsets is None else len(offsets) - 1
     evd = L.events_to_device(ev, dev)
     mu_d = torch.as_tensor(mu, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -139,16 +175,21 @@ def main():
     if args.event_tile:
         ctx.set_tuning(args.event_tile)
     t0 = time.time()
-    evs = L.lmosem_events_load(ctx.handle, evd)
+    evs = L.lmosem_events_load(ctx.handle, evd, offsets)
     torch.cuda.synchronize()
     t_load = time.time() - t0
-    img = torch.as_tensor((mu > 0).astype(np.float32), device=dev).contiguous()
+    t0 = time.time()
+    tile, chunk, graphs = (L.lmosem_autotune(ctx.handle, evs) if not args.event_tile
+                           else (args.event_tile, 256, 1))
+    t_tune = time.time() - t0
+    start = np.broadcast_to((mu > 0).astype(np.float32), (n_real,) + mu.shape).copy()
+    img = torch.as_tensor(start if n_real > 1 else start[0], device=dev).contiguous()
 
     log("warm-up")
     for _ in range(args.warmup):
         L.lmosem_iterate(ctx.handle, evs, 1, img)
     torch.cuda.synchronize()
-    img.copy_(torch.as_tensor((mu > 0).astype(np.float32), device=dev))
+    img.copy_(torch.as_tensor(start if n_real > 1 else start[0], device=dev))
     st0 = L.lmosem_get_stats(ctx.handle)
 
     log(f"timing {args.steps} steps")
@@ -191,7 +232,7 @@ def main():
         "peak": peak_terms * FLOPS_PER_TERM / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved_terms / peak_terms,
-        "traffic": profiled_traffic(ks["event_tile"]),
+        "traffic": profiled_traffic(tile, args.workload),
         "per_unit": "one inner term (event, emission pixel, path end with non-zero position "
                     "response) = 2 FMA + 1 exp2 = 5 flops",
         "units_per_launch": useful_per_launch,
@@ -209,12 +250,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (Monte-Carlo list-mode events from analytic brain phantom)",
-        "config": {"workload": "brain64: 64x64 px of 0.4 cm, 128 bins x 120 angles, 200k events "
-                               "100-175 keV, 8 subsets, exact first-order scatter path",
-                   "events": J, "subsets": g["n_subsets"], "support_pixels": int((mu > 0).sum()),
-                   "event_tile": ks["event_tile"], "path": "exact FP32"},
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "events": J, "realisations": n_real, "subsets": g["n_subsets"],
+                   "support_pixels": int((mu > 0).sum()),
+                   "event_tile": tile, "chunk_rows": chunk, "graphs": bool(graphs), "path": "exact FP32"},
         "roofline": roof,
-        "one_time_ms": {"create_tables": t_create * 1e3, "event_ingest": t_load * 1e3},
+        "one_time_ms": {"create_tables": t_create * 1e3, "event_ingest": t_load * 1e3,
+                        "autotune": t_tune * 1e3},
         "wall_s_timed": wall,
         "skipped_events": ks["skipped_events"],
     }

@@ -206,8 +206,27 @@ void lmosem_events_free(lmosem_evset *set);
 lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters,
                              float *images_dev, double *loglik_host);
 
-/* Tuning: events per forward tile (8, 16 or 32; 0 restores the default). */
+/* Tuning: events per forward tile (8, 16 or 32; 0 restores the default 8)
+ * for event sets loaded afterwards. */
 lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
+
+/* Autotuner: times the forward projection of the set's largest subset for
+ * 8, 16 and 32 events per tile, the backprojection for 128-1024 rows per
+ * chunk, and one whole iteration launched kernel by kernel against one
+ * replayed as a HIP graph; re-plans the set with the fastest choices and
+ * returns them (outputs may be NULL).  With LMOSEM_TUNE_CACHE=<file> in the
+ * environment the choice is looked up in / appended to that file, keyed by
+ * support size, angles, subsets, realisations and subset size.  Results do
+ * not depend on the choice beyond FP32 summation order.  Synchronises. */
+lmosem_status lmosem_autotune(lmosem_ctx *ctx, lmosem_evset *set, int32_t *event_tile,
+                              int32_t *chunk_rows, int32_t *use_graphs);
+
+/* Replay each global iteration of lmosem_iterate / lmosem_reconstruct as one
+ * captured HIP graph (1, the default) or launch kernel by kernel (0); an
+ * autotuned event set follows its own measured choice instead.  The graph
+ * runs on a stream of the context that is ordered after the caller's stream
+ * on entry and before it on exit. */
+lmosem_status lmosem_set_graphs(lmosem_ctx *ctx, int32_t enable);
 
 /* Counters of this context (synchronises the context's stream). */
 lmosem_status lmosem_get_stats(const lmosem_ctx *ctx, lmosem_stats *out);

@@ -27,6 +27,11 @@ struct lmosem_ctx {
     int64_t terms = 0, useful = 0;
     double table_ms = 0.0;
     int64_t table_bytes = 0;
+    // HIP graphs: one captured iteration per prepared set, replayed on an
+    // internal stream ordered after the caller's stream by events
+    bool graphs = true;
+    hipStream_t gst = nullptr;
+    hipEvent_t g_in = nullptr, g_out = nullptr;
     // per-kernel timing (HIP events around each launch while enabled)
     bool timing = false;
     struct Pending { hipEvent_t a, b; int kind; };
@@ -45,6 +50,9 @@ struct lmosem_evset {
     float *pb = nullptr;      // [max_chunks][n_qpad]
     float *f = nullptr;       // [n_real][n_qpad]
     double *ll = nullptr;     // [n_real]
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // one iteration without / with the log-likelihood
+    int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
+    size_t pb_chunks = 0;     // chunk rows allocated in pb
 };
 
 namespace {
@@ -124,13 +132,39 @@ bool check_events(lmosem_ctx *c, const lmosem_events *ev, lmosem_status &st) {
     return true;
 }
 
+void drop_graphs(lmosem_evset *s) {
+    for (auto &x : s->exec)
+        if (x) { hipGraphExecDestroy(x); x = nullptr; }
+}
+
 void free_set(lmosem_evset *s) {
     if (!s) return;
+    drop_graphs(s);
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
     hipFree(s->ll);
     delete s;
+}
+
+// (Re)allocate the per-set workspace for the current tile plan.
+lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
+    const Geo &g = c->g;
+    size_t rows = std::max(s->s.max_rows, 1), groups = forward_groups(g);
+    size_t chunks = std::max(s->s.max_chunks, 1);
+    hipError_t e;
+#define AL(p, bytes) do { if (!(p)) { e = hipMalloc(&(p), (bytes)); if (e != hipSuccess) return alloc_err(c, "workspace", e); } } while (0)
+    AL(s->H, sizeof(float) * rows * g.n_qpad);
+    AL(s->pmean, sizeof(float) * rows * groups);
+    AL(s->mean, sizeof(float) * rows);
+    AL(s->inv, sizeof(float) * rows);
+    if (s->pb && s->pb_chunks < chunks) { hipFree(s->pb); s->pb = nullptr; }
+    if (!s->pb) s->pb_chunks = chunks;
+    AL(s->pb, sizeof(float) * chunks * g.n_qpad);
+    AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
+    AL(s->ll, sizeof(double) * s->s.n_real);
+#undef AL
+    return LMOSEM_OK;
 }
 
 lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch, int force_subset,
@@ -156,18 +190,8 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
         free_set(s);
         return e == hipErrorOutOfMemory ? set_err(c, LMOSEM_ENOMEM, why) : set_err(c, LMOSEM_EDEVICE, why);
     }
-    const Geo &g = c->g;
-    size_t rows = std::max(s->s.max_rows, 1), groups = forward_groups(g);
-    size_t chunks = std::max(s->s.max_chunks, 1);
-#define AL(p, bytes) do { e = hipMalloc(&(p), (bytes)); if (e != hipSuccess) { free_set(s); return alloc_err(c, "workspace", e); } } while (0)
-    AL(s->H, sizeof(float) * rows * g.n_qpad);
-    AL(s->pmean, sizeof(float) * rows * groups);
-    AL(s->mean, sizeof(float) * rows);
-    AL(s->inv, sizeof(float) * rows);
-    AL(s->pb, sizeof(float) * chunks * g.n_qpad);
-    AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
-    AL(s->ll, sizeof(double) * s->s.n_real);
-#undef AL
+    lmosem_status ws = alloc_workspace(c, s);
+    if (ws != LMOSEM_OK) { free_set(s); return ws; }
     *out = s;
     return LMOSEM_OK;
 }
@@ -175,14 +199,14 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
 // Run one launch, bracketed by HIP events on the context stream when timing
 // is enabled (kind 0 forward, 1 backprojection, 2 mean/update).
 template <class F>
-hipError_t timed(lmosem_ctx *c, int kind, F &&launch) {
+hipError_t timed(lmosem_ctx *c, int kind, F &&launch, hipStream_t st) {
     if (!c->timing) return launch();
     lmosem_ctx::Pending p{nullptr, nullptr, kind};
     hipError_t e;
     if ((e = hipEventCreate(&p.a)) != hipSuccess) return e;
     if ((e = hipEventCreate(&p.b)) != hipSuccess) { hipEventDestroy(p.a); return e; }
-    if ((e = hipEventRecord(p.a, c->st)) == hipSuccess && (e = launch()) == hipSuccess)
-        e = hipEventRecord(p.b, c->st);
+    if ((e = hipEventRecord(p.a, st)) == hipSuccess && (e = launch()) == hipSuccess)
+        e = hipEventRecord(p.b, st);
     if (e != hipSuccess) { hipEventDestroy(p.a); hipEventDestroy(p.b); return e; }
     c->pending.push_back(p);
     return hipSuccess;
@@ -204,7 +228,7 @@ hipError_t drain_timing(lmosem_ctx *c) {
 }
 
 // One sub-iteration of Eq. 7 on all realisations of a prepared set.
-hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll) {
+hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hipStream_t st) {
     const Geo &g = c->g;
     const EvSet &v = s->s;
     const int rows = v.row_off[i + 1] - v.row_off[i];
@@ -218,38 +242,84 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll) {
     if (n_tiles > 0 &&
         (e = timed(c, 0, [&] {
              return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], n_tiles, v.u, v.e, v.efac, s->f,
-                                   s->H, s->pmean, v.row_off[i], rows, c->st);
-         })) != hipSuccess)
+                                   s->H, s->pmean, v.row_off[i], rows, st);
+         }, st)) != hipSuccess)
         return e;
     if (rows > 0 &&
-        (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, c->st); })) !=
+        (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, st); }, st)) !=
             hipSuccess)
         return e;
-    if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, c->st)) != hipSuccess)
+    if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, st)) != hipSuccess)
         return e;
     if (n_chunks > 0 &&
         (e = timed(c, 1, [&] {
-             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, s->H, s->inv, s->pb, c->st);
-         })) != hipSuccess)
+             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, s->H, s->inv, s->pb, st);
+         }, st)) != hipSuccess)
         return e;
-    if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, c->st); })) != hipSuccess)
+    if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, st); }, st)) != hipSuccess)
         return e;
-    c->terms += v.terms_sub[i];
-    c->useful += v.useful_sub[i];
+    return hipSuccess;
+}
+
+void count_terms(lmosem_ctx *c, const lmosem_evset *s) {
+    for (int i = 0; i < c->g.n_subsets; ++i) {
+        c->terms += s->s.terms_sub[i];
+        c->useful += s->s.useful_sub[i];
+    }
+}
+
+// Capture one global iteration (all sub-iterations in order; with want_ll the
+// log-likelihood accumulator is cleared by a fill kernel first) as a graph.
+hipError_t capture_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
+    hipError_t e;
+    if (!c->gst) {
+        if ((e = hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&c->g_in, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&c->g_out, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    hipGraph_t graph = nullptr;
+    if ((e = hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t body = hipSuccess;
+    if (want_ll) body = launch_fill_d(s->ll, s->s.n_real, 0.0, c->gst);
+    for (int i = 0; i < c->g.n_subsets && body == hipSuccess; ++i) body = subiteration(c, s, i, want_ll, c->gst);
+    e = hipStreamEndCapture(c->gst, &graph);
+    if (body != hipSuccess) { if (graph) hipGraphDestroy(graph); return body; }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&s->exec[want_ll ? 1 : 0], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    return e;
+}
+
+// One global iteration: replay the captured graph on the internal stream,
+// ordered after and before the caller's stream by events; plain launches on
+// the caller's stream while kernel timing is on or graphs are disabled.
+hipError_t one_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
+    hipError_t e;
+    const bool graph = s->use_graph >= 0 ? s->use_graph == 1 : c->graphs;
+    if (!graph || c->timing) {
+        if (want_ll && (e = launch_fill_d(s->ll, s->s.n_real, 0.0, c->st)) != hipSuccess) return e;
+        for (int i = 0; i < c->g.n_subsets; ++i)
+            if ((e = subiteration(c, s, i, want_ll, c->st)) != hipSuccess) return e;
+    } else {
+        const int k = want_ll ? 1 : 0;
+        if (!s->exec[k] && (e = capture_iteration(c, s, want_ll)) != hipSuccess) return e;
+        if ((e = hipEventRecord(c->g_in, c->st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c->gst, c->g_in, 0)) != hipSuccess) return e;
+        if ((e = hipGraphLaunch(s->exec[k], c->gst)) != hipSuccess) return e;
+        if ((e = hipEventRecord(c->g_out, c->gst)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c->st, c->g_out, 0)) != hipSuccess) return e;
+    }
+    count_terms(c, s);
     return hipSuccess;
 }
 
 lmosem_status iterate_set(lmosem_ctx *c, lmosem_evset *s, int n_iters, double *ll_host) {
-    const Geo &g = c->g;
     std::vector<double> ll;
     if (ll_host) ll.assign((size_t)s->s.n_real * n_iters, 0.0);
     std::vector<double> tmp(s->s.n_real);
     hipError_t e;
     for (int it = 0; it < n_iters; ++it) {
-        if (ll_host && (e = launch_fill_d(s->ll, s->s.n_real, 0.0, c->st)) != hipSuccess)
-            return dev_err(c, "clear loglik", e);
-        for (int i = 0; i < g.n_subsets; ++i)
-            if ((e = subiteration(c, s, i, ll_host != nullptr)) != hipSuccess) return dev_err(c, "sub-iteration", e);
+        if ((e = one_iteration(c, s, ll_host != nullptr)) != hipSuccess) return dev_err(c, "iteration", e);
         if (ll_host) {
             if ((e = hipMemcpyAsync(tmp.data(), s->ll, sizeof(double) * s->s.n_real, hipMemcpyDeviceToHost,
                                     c->st)) != hipSuccess ||
@@ -354,6 +424,10 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
 void lmosem_destroy(lmosem_ctx *c) {
     if (!c) return;
     drain_timing(c);
+    if (c->gst) hipStreamSynchronize(c->gst);
+    if (c->g_in) hipEventDestroy(c->g_in);
+    if (c->g_out) hipEventDestroy(c->g_out);
+    if (c->gst) hipStreamDestroy(c->gst);
     hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted);
     hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;
@@ -440,7 +514,8 @@ lmosem_status lmosem_subset_update(lmosem_ctx *c, int32_t subset, const lmosem_e
     if (st != LMOSEM_OK) return st;
     const Geo &g = c->g;
     hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
-    if (e == hipSuccess) e = subiteration(c, s, subset, false);
+    if (e == hipSuccess) e = subiteration(c, s, subset, false, c->st);
+    if (e == hipSuccess) { c->terms += s->s.terms_sub[subset]; c->useful += s->s.useful_sub[subset]; }
     if (e == hipSuccess && event_mean_dev)
         e = launch_scatter_rows(s->mean, s->s.orig + s->s.row_off[subset],
                                 s->s.row_off[subset + 1] - s->s.row_off[subset], event_mean_dev, c->st);
@@ -502,6 +577,142 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *c, int32_t event_tile) {
     if (event_tile != 8 && event_tile != 16 && event_tile != 32)
         return set_err(c, LMOSEM_EINVAL, "event_tile must be 8, 16 or 32");
     c->ev_tile = event_tile;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_set_graphs(lmosem_ctx *c, int32_t enable) {
+    GUARD(c);
+    c->graphs = enable != 0;
+    return LMOSEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string tune_key(const lmosem_ctx *c, const lmosem_evset *s) {
+    int lg = 0;
+    while ((1 << (lg + 1)) <= std::max(1, s->s.max_rows)) ++lg;
+    char buf[160];
+    snprintf(buf, sizeof buf, "np=%d na=%d ns=%d real=%d rows2^%d", c->g.n_p, c->g.n_angles, c->g.n_subsets,
+             s->s.n_real, lg);
+    return buf;
+}
+
+bool tune_lookup(const std::string &key, int &ev, int &ch, int &graph) {
+    const char *path = getenv("LMOSEM_TUNE_CACHE");
+    if (!path) return false;
+    FILE *fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof line, fp)) {
+        std::string l(line);
+        size_t bar = l.find('|');
+        if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+        found = sscanf(l.c_str() + bar + 1, "%d %d %d", &ev, &ch, &graph) == 3;
+    }
+    fclose(fp);
+    return found && (ev == 8 || ev == 16 || ev == 32) && ch >= 32 && (graph == 0 || graph == 1);
+}
+
+void tune_store(const std::string &key, int ev, int ch, int graph) {
+    const char *path = getenv("LMOSEM_TUNE_CACHE");
+    if (!path) return;
+    if (FILE *fp = fopen(path, "a")) {
+        fprintf(fp, "%s|%d %d %d\n", key.c_str(), ev, ch, graph);
+        fclose(fp);
+    }
+}
+
+// time one launch sequence on the context stream
+template <class F>
+hipError_t time_ms(lmosem_ctx *c, F &&run, float &ms) {
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) { hipEventDestroy(a); return e; }
+    e = run();   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, c->st);
+    if (e == hipSuccess) e = run();
+    if (e == hipSuccess) e = hipEventRecord(b, c->st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_tile, int32_t *chunk_rows,
+                              int32_t *use_graphs) {
+    GUARD(c);
+    if (!s || s->s.ctx != c) return set_err(c, LMOSEM_EINVAL, "bad event set");
+    const Geo &g = c->g;
+    EvSet &v = s->s;
+    std::string why, key = tune_key(c, s);
+    int best_ev = v.ev_tile, best_ch = v.chunk_rows, best_graph = -1;
+    hipError_t e = hipSuccess;
+    if (!tune_lookup(key, best_ev, best_ch, best_graph)) {
+        best_graph = -1;
+        // the largest subset is the one the choice matters for
+        int big = 0;
+        for (int i = 1; i < g.n_subsets; ++i)
+            if (v.row_off[i + 1] - v.row_off[i] > v.row_off[big + 1] - v.row_off[big]) big = i;
+        const int rows = v.row_off[big + 1] - v.row_off[big];
+        float best = 3.4e38f;
+        for (int ev : {8, 16, 32}) {
+            if ((e = plan_tiles(g, c->t, v, ev, v.chunk_rows, c->st, why)) != hipSuccess) break;
+            lmosem_status ws = alloc_workspace(c, s);
+            if (ws != LMOSEM_OK) return ws;
+            float ms = 0.0f;
+            e = time_ms(c, [&] {
+                return launch_forward(ev, g, c->t, v.tiles + v.tile_off[big], v.tile_off[big + 1] - v.tile_off[big],
+                                      v.u, v.e, v.efac, s->f, s->H, s->pmean, v.row_off[big], rows, c->st);
+            }, ms);
+            if (e != hipSuccess) break;
+            if (ms < best) { best = ms; best_ev = ev; }
+        }
+        best = 3.4e38f;
+        for (int ch : {128, 256, 512, 1024}) {
+            if (e != hipSuccess) break;
+            if ((e = plan_tiles(g, c->t, v, best_ev, ch, c->st, why)) != hipSuccess) break;
+            lmosem_status ws = alloc_workspace(c, s);
+            if (ws != LMOSEM_OK) return ws;
+            float ms = 0.0f;
+            e = time_ms(c, [&] {
+                return launch_backproject(g, v.chunks + v.chunk_off[big], v.chunk_off[big + 1] - v.chunk_off[big],
+                                          s->H, s->inv, s->pb, c->st);
+            }, ms);
+            if (e == hipSuccess && ms < best) { best = ms; best_ch = ch; }
+        }
+    }
+    if (e == hipSuccess) e = plan_tiles(g, c->t, v, best_ev, best_ch, c->st, why);
+    if (e != hipSuccess) return dev_err(c, "autotune", e);
+    lmosem_status ws = alloc_workspace(c, s);
+    if (ws != LMOSEM_OK) return ws;
+    drop_graphs(s);
+    if (best_graph < 0) {
+        // one full iteration launched directly versus replayed as a graph
+        // (on a scratch image: the caller's images are gathered at the next
+        // lmosem_iterate)
+        float ms_direct = 0.0f, ms_graph = 0.0f;
+        e = launch_fill(s->f, (size_t)v.n_real * g.n_qpad, 1.0f, c->st);
+        s->use_graph = 0;
+        if (e == hipSuccess) e = time_ms(c, [&] { return one_iteration(c, s, false); }, ms_direct);
+        s->use_graph = 1;
+        if (e == hipSuccess) e = time_ms(c, [&] { return one_iteration(c, s, false); }, ms_graph);
+        if (e != hipSuccess) return dev_err(c, "autotune", e);
+        best_graph = ms_graph < ms_direct ? 1 : 0;
+        tune_store(key, best_ev, best_ch, best_graph);
+    }
+    s->use_graph = best_graph;
+    if (event_tile) *event_tile = best_ev;
+    if (chunk_rows) *chunk_rows = best_ch;
+    if (use_graphs) *use_graphs = best_graph;
     return LMOSEM_OK;
 }
 

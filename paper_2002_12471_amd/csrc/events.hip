@@ -131,10 +131,9 @@ hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,
     int *idx = nullptr, *idx2 = nullptr, *counts = nullptr;
     int64_t *offs_d = nullptr;
     void *tmp = nullptr;
-    long long *terms_d = nullptr, *useful_d = nullptr;
     auto cleanup = [&]() {
         hipFree(keys); hipFree(keys2); hipFree(idx); hipFree(idx2); hipFree(counts);
-        hipFree(offs_d); hipFree(tmp); hipFree(terms_d); hipFree(useful_d);
+        hipFree(offs_d); hipFree(tmp);
     };
 #define CK(call, what) do { e = (call); if (e != hipSuccess) { err = std::string(what) + ": " + hipGetErrorString(e); cleanup(); return e; } } while (0)
     set.n = n;
@@ -170,21 +169,39 @@ hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,
                            ev.energy_kev, set.u, set.e, set.efac, set.orig, counts);
         CK(hipGetLastError(), "gather events");
     }
-    std::vector<int> cnt(std::max(n_groups, 1), 0);
-    CK(hipMemcpyAsync(cnt.data(), counts, sizeof(int) * std::max(n_groups, 1), hipMemcpyDeviceToHost, st),
+    set.counts.assign(std::max(n_groups, 1), 0);
+    CK(hipMemcpyAsync(set.counts.data(), counts, sizeof(int) * std::max(n_groups, 1), hipMemcpyDeviceToHost, st),
        "download counts");
     CK(hipStreamSynchronize(st), "ingest");
+    cleanup();
+#undef CK
+    return plan_tiles(g, tb, set, set.ev_tile, set.chunk_rows, st, err);
+}
 
-    // host planning: tiles per (subset, realisation, angle) group, chunks per
-    // (subset, realisation)
-    const int EV = set.ev_tile;
-    const int CH = 256;   // rows per backprojection chunk
+// Tiles of ev_tile consecutive events per (subset, realisation, angle) group
+// and backprojection chunks of chunk_rows rows per (subset, realisation), from
+// the group counts of the sorted set; replaces any earlier plan.
+hipError_t plan_tiles(const Geo &g, const Tables &tb, EvSet &set, int ev_tile, int chunk_rows,
+                      hipStream_t st, std::string &err) {
+    hipError_t e = hipSuccess;
+    long long *terms_d = nullptr, *useful_d = nullptr;
+    auto cleanup = [&]() { hipFree(terms_d); hipFree(useful_d); };
+#define CK(call, what) do { e = (call); if (e != hipSuccess) { err = std::string(what) + ": " + hipGetErrorString(e); cleanup(); return e; } } while (0)
+    hipFree(set.tiles); hipFree(set.chunks); hipFree(set.crange); hipFree(set.rrange);
+    set.tiles = nullptr; set.chunks = nullptr; set.crange = nullptr; set.rrange = nullptr;
+    set.ev_tile = ev_tile;
+    set.chunk_rows = chunk_rows;
+    const int n_real = set.n_real;
+    const std::vector<int> &cnt = set.counts;
+    const int EV = ev_tile, CH = chunk_rows;
     std::vector<Tile> tiles;
     std::vector<Chunk> chunks;
     std::vector<int> crange, rrange;
     set.row_off.assign(g.n_subsets + 1, 0);
     set.tile_off.assign(g.n_subsets + 1, 0);
     set.chunk_off.assign(g.n_subsets + 1, 0);
+    set.max_rows = 0;
+    set.max_chunks = 0;
     int64_t pos = 0;
     for (int i = 0; i < g.n_subsets; ++i) {
         set.row_off[i] = (int)pos;

@@ -73,6 +73,8 @@ hipError_t validate_events(const Geo &g, const lmosem_events &ev, int64_t *bad_h
 hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
                        const std::vector<int64_t> &offs, int force_subset, EvSet &set,
                        hipStream_t st, std::string &err);
+hipError_t plan_tiles(const Geo &g, const Tables &t, EvSet &set, int ev_tile, int chunk_rows,
+                      hipStream_t st, std::string &err);
 
 // ---- per sub-iteration kernels (osem.hip) ----
 int forward_groups(const Geo &g);
@@ -110,7 +112,9 @@ struct EvSet {
     lmosem_ctx *ctx = nullptr;
     int n_real = 0;
     int64_t n = 0;
-    int ev_tile = 16;
+    int ev_tile = 8;
+    int chunk_rows = 256;   // rows per backprojection chunk
+    std::vector<int> counts;   // events per (subset, realisation, angle) group
     // sorted SoA
     float *u = nullptr;      // detector position, cm
     float *e = nullptr;      // energy minus the encoding centre, keV

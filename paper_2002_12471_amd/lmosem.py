@@ -83,6 +83,9 @@ _sigs = {
     "lmosem_set_tuning": (_S, [_P, ctypes.c_int32]),
     "lmosem_get_stats": (_S, [_P, ctypes.POINTER(lmosem_stats)]),
     "lmosem_set_timing": (_S, [_P, ctypes.c_int32]),
+    "lmosem_autotune": (_S, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32)]),
+    "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
     "lmosem_measure_alu_rates": (_S, [_P, ctypes.POINTER(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _sigs.items():
@@ -231,6 +234,19 @@ def lmosem_get_stats(ctx) -> dict:
 
 def lmosem_set_timing(ctx, enable: bool):
     _check(ctx, _lib.lmosem_set_timing(ctx, 1 if enable else 0))
+
+
+def lmosem_autotune(ctx, evset) -> tuple:
+    """Returns (events per tile, rows per backprojection chunk, graphs 0/1)."""
+    ev = ctypes.c_int32()
+    ch = ctypes.c_int32()
+    gr = ctypes.c_int32()
+    _check(ctx, _lib.lmosem_autotune(ctx, evset, ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(gr)))
+    return ev.value, ch.value, gr.value
+
+
+def lmosem_set_graphs(ctx, enable: bool):
+    _check(ctx, _lib.lmosem_set_graphs(ctx, 1 if enable else 0))
 
 
 def lmosem_measure_alu_rates(stream: torch.cuda.Stream | None = None) -> dict:

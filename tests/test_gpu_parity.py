@@ -239,3 +239,49 @@ def test_reconstruct_brain_geometry_small_event_count(brain, dev):
     f_ref, _ = O.os_lm_mlem(H, ev["angle"], sens, 10, np.ones(len(m.support)), ns)
     ok, worst = _image_ok(img.ravel()[m.support], f_ref)
     assert ok, worst
+
+
+def test_graph_replays_match_kernel_by_kernel(tiny, dev):
+    # every replay of the captured iteration is compared with the same
+    # iteration launched kernel by kernel, with eager work in between
+    L, ctx, mu = tiny["L"], tiny["ctx"], tiny["mu"]
+    g4 = dict(tiny["g"], n_subsets=4)
+    c4 = L.Context(g4, torch.as_tensor(mu, device=dev))
+    ev = L.lmosem_events_load(c4.handle, tiny["evd"])
+    try:
+        start = torch.as_tensor((mu > 0).astype(np.float32), device=dev)
+        a = start.clone()
+        b = start.clone()
+        for it in range(4):
+            want_ll = it % 2 == 1
+            L.lmosem_set_graphs(c4.handle, False)
+            ll_a = L.lmosem_iterate(c4.handle, ev, 1, a, want_loglik=want_ll)
+            junk = torch.randn(4096, device=dev).cumsum(0)   # unrelated eager work
+            torch.cuda.synchronize()
+            L.lmosem_set_graphs(c4.handle, True)
+            ll_b = L.lmosem_iterate(c4.handle, ev, 1, b, want_loglik=want_ll)
+            torch.cuda.synchronize()
+            assert float(junk[-1]) == float(junk[-1])
+            assert torch.equal(a, b), it
+            if want_ll:
+                assert np.array_equal(ll_a, ll_b)
+    finally:
+        L.lmosem_events_free(ev)
+        c4.close()
+
+
+def test_autotune_keeps_results(tiny, dev):
+    L, ctx, mu = tiny["L"], tiny["ctx"], tiny["mu"]
+    start = torch.as_tensor((mu > 0).astype(np.float32), device=dev)
+    ev = L.lmosem_events_load(ctx.handle, tiny["evd"])
+    try:
+        a = start.clone()
+        L.lmosem_iterate(ctx.handle, ev, 3, a)
+        tile, chunk, graphs = L.lmosem_autotune(ctx.handle, ev)
+        assert tile in (8, 16, 32) and chunk in (128, 256, 512, 1024) and graphs in (0, 1)
+        b = start.clone()
+        L.lmosem_iterate(ctx.handle, ev, 3, b)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=2e-6, atol=1e-12)
+    finally:
+        L.lmosem_events_free(ev)
