@@ -71,6 +71,7 @@ typedef enum {
 
 typedef struct lmosem_ctx lmosem_ctx;
 typedef struct lmosem_evset lmosem_evset;
+typedef struct lmosem_net lmosem_net;
 
 /* Geometry and physics of one acquisition (all units explicit). */
 typedef struct {
@@ -87,7 +88,9 @@ typedef struct {
     double win_lo_kev;        /* accepted energies [win_lo, win_hi]: photopeak */
     double win_hi_kev;        /*   and scatter windows together */
     int32_t n_subsets;        /* 1 .. n_angles */
-    int32_t scatter_model;    /* 0: primary paths only; 1: primary + first-order scatter */
+    int32_t scatter_model;    /* 0: primary paths only; 1: primary + first-order scatter;
+                                 2: primary + learned first-order scatter (needs a network,
+                                 lmosem_set_surrogate; no path table is stored) */
     double acq_time;          /* T (> 0) */
 } lmosem_config;
 
@@ -240,6 +243,46 @@ lmosem_status lmosem_set_timing(lmosem_ctx *ctx, int32_t enable);
  * two FMAs and one exp2 that the forward projection issues per term (in
  * terms per second).  Runs short probe kernels on hip_stream (synchronises). */
 lmosem_status lmosem_measure_alu_rates(void *hip_stream, double *out3);
+
+/* ---- learned scatter surrogate -------------------------------------
+ * Not part of the paper: a network S_net(x) replaces the first-order scatter
+ * part of each system row, S(q; a, u, E) = sum_{s != q} s_eff-weighted
+ * K G terms (Sec. 2.2), one evaluation per (event, emission pixel), while
+ * the primary term stays exact.  Network: 8 -> 128 -> 128 -> 128 -> 1, GELU
+ * (tanh form), bf16 weights and activations with FP32 accumulation on MFMA,
+ * FP32 master weights, Adam.  Inputs x (8 floats per pair) and the target
+ * y = ln(S / S0 + 1e-4), S0 = 1 / (pixel_cm * sigma_E), are produced by
+ * lmosem_surrogate_samples.  Parameters are passed flat (34305 floats):
+ * W1[8][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[128] b4,
+ * W[in][out]. */
+
+/* New network from host parameters; its kernels run on hip_stream. */
+lmosem_status lmosem_net_create(const float *params_host, void *hip_stream, lmosem_net **out);
+void lmosem_net_destroy(lmosem_net *net);
+/* Current FP32 master parameters into params_host[34305] (synchronises). */
+lmosem_status lmosem_net_get_params(lmosem_net *net, float *params_host);
+/* y_dev[n] = network(X_dev[n][8]). */
+lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n, float *y_dev);
+/* Gradient of sum_i dy_dev[i] y_i over all parameters into grad_host[34305];
+ * n a positive multiple of 16 (synchronises). */
+lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const float *dy_dev, int32_t n,
+                                  float *grad_host);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) on the mean-squared error over
+ * minibatches of `batch` samples taken in order (the caller shuffles);
+ * lr is multiplied by lr_decay after each epoch; loss_host (nullable)
+ * receives each epoch's mean loss. */
+lmosem_status lmosem_net_train(lmosem_net *net, const float *X_dev, const float *t_dev, int64_t n, int32_t batch,
+                               int32_t epochs, float lr, float lr_decay, double *loss_host);
+/* Training samples on a scatter_model-1 context: for each (support pixel,
+ * angle, u_bin, energy) the network inputs X_dev[n][8], the target
+ * target_dev[n] and (nullable) the exact scatter sum scatter_dev[n], from the
+ * exact path table.  Errors: ENOTSUP without a path table, ERANGE. */
+lmosem_status lmosem_surrogate_samples(lmosem_ctx *ctx, const int32_t *pixel, const int32_t *angle,
+                                       const float *u_bin, const float *energy, int64_t n, float *X_dev,
+                                       float *target_dev, float *scatter_dev);
+/* Use `net` (not owned; keep it alive) for the scatter term of a
+ * scatter_model-2 context. */
+lmosem_status lmosem_set_surrogate(lmosem_ctx *ctx, lmosem_net *net);
 
 #ifdef __cplusplus
 }

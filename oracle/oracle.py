@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liblmosem_oracle.so")
 _lib = None
 
 __all__ = ["build", "OracleModel", "os_lm_mlem", "subset_update", "log_likelihood",
+           "surrogate_features", "surrogate_target",
            "compton_energy", "kn_shape", "kn_total", "rho", "psi_bar", "resp_K", "resp_D",
            "resp_G", "resp_W", "line_integral", "circle_mean", "default_threads"]
 
@@ -252,6 +253,35 @@ class OracleModel:
         img = np.zeros(self.n * self.n, np.float64)
         img[q] = vec
         return img.reshape(self.n, self.n)
+
+
+# ---------------------------------------------------------------- surrogate references
+def surrogate_features(model: "OracleModel", pixel: int, a: int, u_cm: float, e_kev: float) -> np.ndarray:
+    """Inputs of the scatter surrogate for (pixel, angle, position, energy):
+    pixel position in the detector frame, offset of the event from it,
+    energy, attenuation from the pixel toward and away from the detector,
+    attenuation along the event's whole detector line, and mu at the pixel
+    (each with the fixed scale the network uses)."""
+    g = model.geom
+    n, dx = model.n, float(g["pixel_cm"])
+    th = float(g.get("angle0_rad", 0.0)) + 2 * np.pi * a / int(g["n_angles"])
+    nvec = np.array([np.cos(th), np.sin(th)])
+    tvec = np.array([-np.sin(th), np.cos(th)])
+    c = np.array([((pixel % n) - (n - 1) / 2) * dx, ((pixel // n) - (n - 1) / 2) * dx])
+    far = 4.0 * n * dx
+    uq, dq = float(c @ tvec), float(c @ nvec)
+    to_det = line_integral(model.mu, dx, c, c + far * nvec)
+    away = line_integral(model.mu, dx, c, c - far * nvec)
+    foot = u_cm * tvec
+    chord = line_integral(model.mu, dx, foot - far * nvec, foot + far * nvec)
+    return np.array([uq / 10, dq / 10, (u_cm - uq) / 2, (e_kev - 130) / 30, to_det, away, chord / 2,
+                     10 * model.mu.flat[pixel]])
+
+
+def surrogate_target(scatter_sum: float, geom: dict, floor: float = 1e-4) -> float:
+    """Training target of the surrogate: ln(S / S0 + floor), S0 = 1 / (pixel_cm sigma_E)."""
+    sig_e = float(geom["fwhm_e_kev"]) / (2 * np.sqrt(2 * np.log(2)))
+    return float(np.log(scatter_sum * float(geom["pixel_cm"]) * sig_e + floor))
 
 
 # ---------------------------------------------------------------- EM algebra

@@ -24,6 +24,8 @@ struct lmosem_ctx {
     int ev_tile = 8;
     int *bad_dev = nullptr;
     unsigned long long *skipped_dev = nullptr;
+    bool surrogate = false;        // scatter_model 2: network scatter term
+    lmo::Net *net = nullptr;       // attached network (not owned)
     int64_t terms = 0, useful = 0;
     double table_ms = 0.0;
     int64_t table_bytes = 0;
@@ -52,10 +54,15 @@ struct lmosem_evset {
     double *ll = nullptr;     // [n_real]
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // one iteration without / with the log-likelihood
     int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
+    float *chord = nullptr;   // surrogate: per-event line attenuation [n]
+    float *X = nullptr;       // surrogate: network inputs [pair_cap][8]
+    float *y = nullptr;       // surrogate: network outputs [pair_cap]
     size_t pb_chunks = 0;     // chunk rows allocated in pb
 };
 
 namespace {
+
+constexpr int64_t kPairCap = 1 << 20;   // (event, pixel) pairs per surrogate network batch
 
 lmosem_status set_err(lmosem_ctx *c, lmosem_status s, const std::string &msg) {
     if (c) {
@@ -108,8 +115,8 @@ bool check_cfg(const lmosem_config *c, std::string &why) {
     }
     if (!(c->win_lo_kev < c->win_hi_kev) || !(c->win_lo_kev > 0)) { why = "need 0 < win_lo < win_hi"; return false; }
     if (c->n_subsets < 1 || c->n_subsets > c->n_angles) { why = "need 1 <= n_subsets <= n_angles"; return false; }
-    if (c->scatter_model != 0 && c->scatter_model != 1) {
-        why = "scatter_model must be 0 (primary) or 1 (first-order scatter)";
+    if (c->scatter_model < 0 || c->scatter_model > 2) {
+        why = "scatter_model must be 0 (primary), 1 (first-order scatter) or 2 (learned scatter)";
         return false;
     }
     if (!(c->acq_time > 0)) { why = "acq_time must be > 0"; return false; }
@@ -143,7 +150,7 @@ void free_set(lmosem_evset *s) {
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
-    hipFree(s->ll);
+    hipFree(s->ll); hipFree(s->chord); hipFree(s->X); hipFree(s->y); hipFree(s->s.ang);
     delete s;
 }
 
@@ -163,6 +170,11 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
     AL(s->pb, sizeof(float) * chunks * g.n_qpad);
     AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
     AL(s->ll, sizeof(double) * s->s.n_real);
+    if (c->surrogate) {
+        AL(s->chord, sizeof(float) * (size_t)std::max<int64_t>(s->s.n, 1));
+        AL(s->X, sizeof(float) * 8 * (size_t)kPairCap);
+        AL(s->y, sizeof(float) * (size_t)kPairCap);
+    }
 #undef AL
     return LMOSEM_OK;
 }
@@ -170,6 +182,7 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
 lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch, int force_subset,
                        lmosem_evset **out) {
     lmosem_status st = LMOSEM_OK;
+    if (c->surrogate && !c->net) return set_err(c, LMOSEM_ESTATE, "scatter_model 2 needs a network (lmosem_set_surrogate)");
     if (!check_events(c, ev, st)) return st;
     std::vector<int64_t> offs;
     if (batch) {
@@ -227,6 +240,21 @@ hipError_t drain_timing(lmosem_ctx *c) {
     return e;
 }
 
+// System rows and partial means of subset i: exact forward projection, or
+// exact primaries plus the network's scatter term.
+hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, hipStream_t st) {
+    const Geo &g = c->g;
+    const EvSet &v = s->s;
+    const int rows = v.row_off[i + 1] - v.row_off[i];
+    if (c->surrogate)
+        return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
+                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->chord, s->X, s->y, kPairCap, st);
+    return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
+                          v.efac, s->f, s->H, s->pmean, v.row_off[i], rows, st);
+}
+
+int mean_groups(const lmosem_ctx *c) { return c->surrogate ? 1 : forward_groups(c->g); }
+
 // One sub-iteration of Eq. 7 on all realisations of a prepared set.
 hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hipStream_t st) {
     const Geo &g = c->g;
@@ -234,16 +262,13 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     const int rows = v.row_off[i + 1] - v.row_off[i];
     const int n_tiles = v.tile_off[i + 1] - v.tile_off[i];
     const int n_chunks = v.chunk_off[i + 1] - v.chunk_off[i];
-    const int groups = forward_groups(g);
+    const int groups = mean_groups(c);
     const float *sens = c->t.sens + (size_t)i * g.n_qpad;
     const int *crange = v.crange + (size_t)i * (v.n_real + 1);
     const int *rrange = v.rrange + (size_t)i * (v.n_real + 1);
     hipError_t e;
-    if (n_tiles > 0 &&
-        (e = timed(c, 0, [&] {
-             return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], n_tiles, v.u, v.e, v.efac, s->f,
-                                   s->H, s->pmean, v.row_off[i], rows, st);
-         }, st)) != hipSuccess)
+    if ((n_tiles > 0 || (c->surrogate && rows > 0)) &&
+        (e = timed(c, 0, [&] { return forward_rows(c, s, i, st); }, st)) != hipSuccess)
         return e;
     if (rows > 0 &&
         (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, st); }, st)) !=
@@ -295,7 +320,8 @@ hipError_t capture_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
 // the caller's stream while kernel timing is on or graphs are disabled.
 hipError_t one_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
     hipError_t e;
-    const bool graph = s->use_graph >= 0 ? s->use_graph == 1 : c->graphs;
+    // the surrogate path allocates network workspace lazily: never captured
+    const bool graph = !c->surrogate && (s->use_graph >= 0 ? s->use_graph == 1 : c->graphs);
     if (!graph || c->timing) {
         if (want_ll && (e = launch_fill_d(s->ll, s->s.n_real, 0.0, c->st)) != hipSuccess) return e;
         for (int i = 0; i < c->g.n_subsets; ++i)
@@ -373,7 +399,8 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     g.n_qpad = (g.n_p + 63) / 64 * 64;
     g.n_rpad = g.n_p + kRankPad;
     g.n_angles = cfg->n_angles; g.n_bins = cfg->n_bins; g.n_subsets = cfg->n_subsets;
-    g.scatter = cfg->scatter_model;
+    g.scatter = cfg->scatter_model != 0;
+    c->surrogate = cfg->scatter_model == 2;
     g.dx = cfg->pixel_cm; g.bin_cm = cfg->bin_cm; g.half_len = 0.5 * cfg->n_bins * cfg->bin_cm;
     g.e0 = cfg->e0_kev; g.kappa = cfg->e0_kev / kMeC2;
     const double fw = 2.0 * sqrt(2.0 * log(2.0));
@@ -407,7 +434,7 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     CK(hipMemcpyAsync(c->t.cs, cs.data(), sizeof(double) * 2 * g.n_angles, hipMemcpyHostToDevice, c->st), "upload");
 #undef CK
     std::string err;
-    e = build_tables(g, c->t, c->st, err, c->table_bytes);
+    e = build_tables(g, c->t, !c->surrogate, c->st, err, c->table_bytes);
     if (e != hipSuccess) {
         lmosem_destroy(c);
         return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE;
@@ -429,7 +456,8 @@ void lmosem_destroy(lmosem_ctx *c) {
     if (c->g_out) hipEventDestroy(c->g_out);
     if (c->gst) hipStreamDestroy(c->gst);
     hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted);
-    hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->bad_dev); hipFree(c->skipped_dev);
+    hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->t.Ldet); hipFree(c->t.Lback);
+    hipFree(c->t.prim); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;
 }
 
@@ -535,11 +563,8 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
     const EvSet &v = s->s;
     const int rows = v.row_off[1];
     hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
-    if (e == hipSuccess)
-        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, v.efac, s->f, s->H, s->pmean, 0,
-                           rows, c->st);
-    if (e == hipSuccess)
-        e = launch_mean(s->pmean, forward_groups(g), rows, s->mean, s->inv, c->skipped_dev, c->st);
+    if (e == hipSuccess) e = forward_rows(c, s, 0, c->st);
+    if (e == hipSuccess) e = launch_mean(s->pmean, mean_groups(c), rows, s->mean, s->inv, c->skipped_dev, c->st);
     if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e == hipSuccess) { c->terms += v.terms_sub[0]; c->useful += v.useful_sub[0]; }
@@ -558,9 +583,7 @@ lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const f
     const EvSet &v = s->s;
     const int rows = v.row_off[1];
     hipError_t e = launch_fill(s->f, (size_t)g.n_qpad, 0.0f, c->st);
-    if (e == hipSuccess)
-        e = launch_forward(v.ev_tile, g, c->t, v.tiles, v.tile_off[1], v.u, v.e, v.efac, s->f, s->H, s->pmean, 0,
-                           rows, c->st);
+    if (e == hipSuccess) e = forward_rows(c, s, 0, c->st);
     if (e == hipSuccess) e = launch_gather_rows(weights_dev, v.orig, rows, s->inv, c->st);
     if (e == hipSuccess) e = launch_backproject(g, v.chunks, v.chunk_off[1], s->H, s->inv, s->pb, c->st);
     if (e == hipSuccess) e = launch_sum_real(g, v.crange, 1, s->pb, s->f, c->st);
@@ -577,6 +600,87 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *c, int32_t event_tile) {
     if (event_tile != 8 && event_tile != 16 && event_tile != 32)
         return set_err(c, LMOSEM_EINVAL, "event_tile must be 8, 16 or 32");
     c->ev_tile = event_tile;
+    return LMOSEM_OK;
+}
+
+struct lmosem_net {
+    lmo::Net *n = nullptr;
+};
+
+lmosem_status lmosem_net_create(const float *params_host, void *hip_stream, lmosem_net **out) {
+    if (!params_host || !out) return LMOSEM_EINVAL;
+    *out = nullptr;
+    lmo::Net *n = nullptr;
+    hipError_t e = net_create(params_host, (hipStream_t)hip_stream, &n);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE;
+    *out = new lmosem_net{n};
+    return LMOSEM_OK;
+}
+
+void lmosem_net_destroy(lmosem_net *net) {
+    if (!net) return;
+    net_destroy(net->n);
+    delete net;
+}
+
+lmosem_status lmosem_net_get_params(lmosem_net *net, float *params_host) {
+    if (!net || !params_host) return LMOSEM_EINVAL;
+    return net_get_params(net->n, params_host) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+}
+
+lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n, float *y_dev) {
+    if (!net || n < 0 || (n > 0 && (!X_dev || !y_dev))) return LMOSEM_EINVAL;
+    return net_forward(net->n, X_dev, n, y_dev) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+}
+
+lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const float *dy_dev, int32_t n,
+                                  float *grad_host) {
+    if (!net || !X_dev || !dy_dev || !grad_host || n <= 0 || n % 16) return LMOSEM_EINVAL;
+    return net_gradient(net->n, X_dev, dy_dev, n, grad_host) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+}
+
+lmosem_status lmosem_net_train(lmosem_net *net, const float *X_dev, const float *t_dev, int64_t n, int32_t batch,
+                               int32_t epochs, float lr, float lr_decay, double *loss_host) {
+    if (!net || !X_dev || !t_dev || batch <= 0 || batch % 16 || n < batch || epochs < 0 || !(lr > 0))
+        return LMOSEM_EINVAL;
+    return net_train(net->n, X_dev, t_dev, n, batch, epochs, lr, lr_decay, loss_host) == hipSuccess ? LMOSEM_OK
+                                                                                                    : LMOSEM_EDEVICE;
+}
+
+lmosem_status lmosem_surrogate_samples(lmosem_ctx *c, const int32_t *pixel, const int32_t *angle,
+                                       const float *u_bin, const float *energy, int64_t n, float *X_dev,
+                                       float *target_dev, float *scatter_dev) {
+    GUARD(c);
+    if (!c->t.T) return set_err(c, LMOSEM_ENOTSUP, "training samples need the exact path table (scatter_model 1)");
+    if (n < 0 || (n > 0 && (!pixel || !angle || !u_bin || !energy || !X_dev || !target_dev)))
+        return set_err(c, LMOSEM_EINVAL, "bad sample arrays");
+    // the samples' angles, positions and energies follow the event rules;
+    // their pixels must lie on the support
+    lmosem_events ev{n, angle, u_bin, energy};
+    lmosem_status st = LMOSEM_OK;
+    if (!check_events(c, &ev, st)) return st;
+    if (n > 0) {
+        std::vector<int32_t> px(n);
+        hipError_t e = hipMemcpyAsync(px.data(), pixel, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) return dev_err(c, "samples", e);
+        std::vector<int> qop(c->g.n_pix);
+        e = hipMemcpy(qop.data(), c->t.p_pix + c->g.n_p, sizeof(int) * c->g.n_pix, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return dev_err(c, "samples", e);
+        for (int32_t p : px)
+            if (p < 0 || p >= c->g.n_pix || qop[p] < 0)
+                return set_err(c, LMOSEM_ERANGE, "sample pixel outside the support");
+    }
+    hipError_t e = surrogate_samples(c->g, c->t, pixel, angle, u_bin, energy, n, X_dev, target_dev, scatter_dev,
+                                     c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "samples", e);
+}
+
+lmosem_status lmosem_set_surrogate(lmosem_ctx *c, lmosem_net *net) {
+    GUARD(c);
+    if (!c->surrogate) return set_err(c, LMOSEM_EINVAL, "the context was not created with scatter_model 2");
+    c->net = net ? net->n : nullptr;
     return LMOSEM_OK;
 }
 
@@ -665,6 +769,7 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
         const int rows = v.row_off[big + 1] - v.row_off[big];
         float best = 3.4e38f;
         for (int ev : {8, 16, 32}) {
+            if (c->surrogate) break;
             if ((e = plan_tiles(g, c->t, v, ev, v.chunk_rows, c->st, why)) != hipSuccess) break;
             lmosem_status ws = alloc_workspace(c, s);
             if (ws != LMOSEM_OK) return ws;
@@ -695,6 +800,7 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
     lmosem_status ws = alloc_workspace(c, s);
     if (ws != LMOSEM_OK) return ws;
     drop_graphs(s);
+    if (c->surrogate) best_graph = 0;
     if (best_graph < 0) {
         // one full iteration launched directly versus replayed as a graph
         // (on a scratch image: the caller's images are gathered at the next

@@ -72,12 +72,14 @@ __global__ void k_keys(Geo g, int64_t n, int n_real, const int64_t *__restrict__
 
 __global__ void k_gather_events(Geo g, int64_t n, const uint64_t *__restrict__ keys,
                                 const int *__restrict__ idx, const float *__restrict__ u_bin,
-                                const float *__restrict__ energy, float *__restrict__ su,
+                                const float *__restrict__ energy, const int32_t *__restrict__ angle,
+                                int *__restrict__ sa, float *__restrict__ su,
                                 float *__restrict__ se, float *__restrict__ efac, int *__restrict__ orig,
                                 int *__restrict__ counts) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int j = idx[k];
+    sa[k] = angle[j];
     su[k] = u_bin[j];
     const double x = (double)energy[j] - g.e_c;
     se[k] = (float)x;
@@ -139,6 +141,7 @@ hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,
     set.n = n;
     set.n_real = n_real;
     size_t nn = (size_t)std::max<int64_t>(n, 1);
+    CK(hipMalloc(&set.ang, sizeof(int) * nn), "alloc events");
     CK(hipMalloc(&set.u, sizeof(float) * nn), "alloc events");
     CK(hipMalloc(&set.e, sizeof(float) * nn), "alloc events");
     CK(hipMalloc(&set.orig, sizeof(int) * nn), "alloc events");
@@ -166,7 +169,7 @@ hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,
         CK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys2, idx, idx2, (int)n, 0,
                                               32 + hi_bits, st), "sort");
         hipLaunchKernelGGL(k_gather_events, dim3(blocks), dim3(256), 0, st, g, n, keys2, idx2, ev.u_bin,
-                           ev.energy_kev, set.u, set.e, set.efac, set.orig, counts);
+                           ev.energy_kev, ev.angle, set.ang, set.u, set.e, set.efac, set.orig, counts);
         CK(hipGetLastError(), "gather events");
     }
     set.counts.assign(std::max(n_groups, 1), 0);

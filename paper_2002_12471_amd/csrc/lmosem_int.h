@@ -61,10 +61,14 @@ struct Tables {
     float2 *T = nullptr;         // [n_angles][n_rpad][n_qpad] (alpha, beta) per path
     float *sens = nullptr;       // [n_subsets][n_qpad]
     float *sens_all = nullptr;   // [n_qpad]
+    float *Ldet = nullptr;       // [n_angles][n_p] attenuation from the pixel centre to the detector
+    float *Lback = nullptr;      // [n_angles][n_p] attenuation from the pixel centre away from it
+    float *prim = nullptr;       // [n_angles][n_p] alpha of each pixel's primary path
 };
 
 // ---- table build (tables.hip) ----
-hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes);
+hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, hipStream_t st, std::string &err,
+                        int64_t &bytes);
 
 // ---- event ingest (events.hip) ----
 struct EvSet;
@@ -104,6 +108,27 @@ hipError_t launch_fill_d(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_check_image(const Geo &g, const Tables &t, const float *img, int *bad,
                               hipStream_t st);
 
+// ---- surrogate network (mlp.hip) and its use (surrogate.hip) ----
+struct Net;
+extern const int kNetParams;
+hipError_t net_create(const float *params_host, hipStream_t st, Net **out);
+void net_destroy(Net *n);
+void net_set_stream(Net *n, hipStream_t st);
+hipError_t net_get_params(Net *n, float *host);
+hipError_t net_forward(Net *n, const float *X, int64_t count, float *y);
+hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host);
+hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
+                     float lr_decay, double *loss_host);
+hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *C, int ldc, int M, int N,
+                   int K, bool accumulate, hipStream_t st);
+hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel, const int32_t *angle,
+                             const float *u_bin, const float *energy, int64_t n, float *X, float *target,
+                             float *scatter, hipStream_t st);
+hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
+                          const float *se, const float *efac, const float *f, const int *rrange, int n_real,
+                          int row_base, int rows, float *H, float *pmean, float *chord, float *X, float *y,
+                          int64_t pair_cap, hipStream_t st);
+
 // ---- ALU rate probes (probe.hip) ----
 hipError_t measure_alu_rates(hipStream_t st, double *out3);
 
@@ -116,6 +141,7 @@ struct EvSet {
     int chunk_rows = 256;   // rows per backprojection chunk
     std::vector<int> counts;   // events per (subset, realisation, angle) group
     // sorted SoA
+    int *ang = nullptr;      // detector angle
     float *u = nullptr;      // detector position, cm
     float *e = nullptr;      // energy minus the encoding centre, keV
     float *efac = nullptr;   // 2^(-c2 e^2) / Z_K per event

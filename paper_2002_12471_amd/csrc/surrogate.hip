@@ -1,0 +1,236 @@
+// Learned scatter surrogate: features, exact training targets, inference.
+//
+// The surrogate replaces the first-order scatter part of the system row,
+//     S(q; a, u, E) = sum_{s != q} w(q,s,a) K(u - u_s(a)) G(E; E'(q,s,a)),
+// by one network evaluation per (event, emission pixel); the primary term is
+// kept exact.  Inputs (all O(1)) for pixel q, angle a, event position u (cm)
+// and energy E (keV):
+//     u_q / 10, d_q / 10       q in the detector frame (u_q = c_q . t_a, d_q = c_q . n_a)
+//     (u - u_q) / 2            event position relative to q's primary position
+//     (E - 130) / 30           energy
+//     L_a(q), L_a^back(q)      attenuation from q toward and away from the detector
+//     C_a(u) / 2               attenuation along the whole detector line through u
+//     10 mu(q)                 attenuation coefficient at q
+// Target: y = ln(S / S0 + 1e-4) with S0 = 1 / (pixel_cm sigma_E); inverse
+// S = S0 max(e^y - 1e-4, 0).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "lmosem_int.h"
+
+namespace lmo {
+
+constexpr float kTargetFloor = 1e-4f;
+
+// attenuation along the whole line {r : r . t = u} (both directions), by
+// boundary-to-boundary traversal from the line's entry into the grid
+__device__ double line_chord(const float *__restrict__ mu, const Geo &g, double nx, double ny, double u) {
+    const double tx = -ny, ty = nx;
+    const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dx;
+    const double px = u * tx, py = u * ty;          // foot of the line on the origin's normal
+    // slab clipping of p + t n against the grid box
+    double t0 = -1e300, t1 = 1e300;
+    const double p[2] = {px, py}, d[2] = {nx, ny}, h[2] = {hx, hy};
+    for (int k = 0; k < 2; ++k) {
+        if (fabs(d[k]) < 1e-300) {
+            if (p[k] <= -h[k] || p[k] >= h[k]) return 0.0;
+        } else {
+            double a = (-h[k] - p[k]) / d[k], b = (h[k] - p[k]) / d[k];
+            if (a > b) { double s = a; a = b; b = s; }
+            t0 = fmax(t0, a);
+            t1 = fmin(t1, b);
+        }
+    }
+    if (t1 <= t0) return 0.0;
+    double sum = 0.0, t = t0;
+    const double ex = px + t0 * nx, ey = py + t0 * ny;
+    // pixel of the entry point, nudged inside along the direction
+    const double eps = 1e-9 * g.dx;
+    int i = (int)floor((ex + eps * nx) / g.dx + 0.5 * g.nx);
+    int j = (int)floor((ey + eps * ny) / g.dx + 0.5 * g.ny);
+    i = min(max(i, 0), g.nx - 1);
+    j = min(max(j, 0), g.ny - 1);
+    const int sx = nx > 0 ? 1 : (nx < 0 ? -1 : 0), sy = ny > 0 ? 1 : (ny < 0 ? -1 : 0);
+    const double inf = 1e300;
+    double tmx = sx ? ((i + (sx > 0 ? 1 : 0) - 0.5 * g.nx) * g.dx - px) / nx : inf;
+    double tmy = sy ? ((j + (sy > 0 ? 1 : 0) - 0.5 * g.ny) * g.dx - py) / ny : inf;
+    const double tdx = sx ? g.dx / fabs(nx) : inf, tdy = sy ? g.dx / fabs(ny) : inf;
+    for (int guard = 0; guard < 4 * (g.nx + g.ny) + 8; ++guard) {
+        const double tn = fmin(fmin(tmx, tmy), t1);
+        if (tn > t) sum += (double)mu[j * g.nx + i] * (tn - t);
+        t = tn;
+        if (t >= t1) break;
+        if (tmx <= tmy) { i += sx; tmx += tdx; } else { j += sy; tmy += tdy; }
+        if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) break;
+    }
+    return sum;
+}
+
+struct SurrTables {
+    const float *Ldet, *Lback;   // [n_angles][n_p]
+    const float *prim;           // [n_angles][n_p] alpha of the primary path
+    const int *p_pix;
+    const float *mu;
+    const double *cs;
+};
+
+__device__ inline void features(const Geo &g, const SurrTables &t, int q, int a, double u, double e,
+                                double chord, float *x) {
+    const int pix = t.p_pix[q];
+    const double cx = ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx, cy = ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx;
+    const double nx = t.cs[2 * a], ny = t.cs[2 * a + 1];
+    const double uq = -ny * cx + nx * cy, dq = nx * cx + ny * cy;
+    x[0] = (float)(uq / 10.0);
+    x[1] = (float)(dq / 10.0);
+    x[2] = (float)((u - uq) / 2.0);
+    x[3] = (float)((e - 130.0) / 30.0);
+    x[4] = t.Ldet[(size_t)a * g.n_p + q];
+    x[5] = t.Lback[(size_t)a * g.n_p + q];
+    x[6] = (float)(chord / 2.0);
+    x[7] = 10.0f * t.mu[pix];
+}
+
+// Training samples: features and the exact target from the path table.
+__global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_of_pix,
+                               const float2 *__restrict__ T, const int *__restrict__ s_sorted,
+                               const double *__restrict__ us_sorted, const int32_t *__restrict__ pixel,
+                               const int32_t *__restrict__ angle, const float *__restrict__ u_bin,
+                               const float *__restrict__ energy, int64_t n, float *__restrict__ X,
+                               float *__restrict__ target, float *__restrict__ scatter) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int q = q_of_pix[pixel[k]];
+    const int a = angle[k];
+    const double u = ((double)u_bin[k] - 0.5 * g.n_bins) * g.bin_cm;
+    const double e = (double)energy[k];
+    const double ec = e - g.e_c;
+    const double efac = exp2(-g.c2 * ec * ec) / g.zk;
+    const double *us = us_sorted + (size_t)a * g.n_p;
+    const double reach = 3.0 * g.sig_u;
+    int lo = 0, hi = g.n_p;   // first rank with us > u - reach
+    while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > u - reach) hi = m; else lo = m + 1; }
+    double s = 0.0;
+    for (int r = lo; r < g.n_p && us[r] < u + reach; ++r) {
+        if (s_sorted[(size_t)a * g.n_p + r] == q) continue;   // the primary path
+        const double d = u - us[r];
+        const double gk = exp(-d * d / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5);
+        if (gk <= 0.0) continue;
+        const float2 ab = T[((size_t)a * g.n_rpad + r) * g.n_qpad + q];
+        s += gk * efac * exp2((double)ab.y * ec + (double)ab.x);
+    }
+    float x[8];
+    features(g, st, q, a, u, e, line_chord(st.mu, g, st.cs[2 * a], st.cs[2 * a + 1], u), x);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) X[k * 8 + i] = x[i];
+    const double s0 = 1.0 / (g.dx * g.sig_e);
+    target[k] = (float)log(s / s0 + (double)kTargetFloor);
+    if (scatter) scatter[k] = (float)s;
+}
+
+// per event: attenuation along its detector line
+__global__ void k_event_chord(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
+                              int n, float *__restrict__ chord) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int a = ev_angle[j];
+    const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
+    chord[j] = (float)line_chord(st.mu, g, st.cs[2 * a], st.cs[2 * a + 1], u);
+}
+
+// Inference, step 1: for rows [j0, j0 + rows) of the sub-iteration and every
+// emission pixel q, the exact primary term into H and the network inputs.
+__global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
+                             const float *__restrict__ se, const float *__restrict__ efac,
+                             const float *__restrict__ chord, int row_base, int j0, int rows,
+                             float *__restrict__ H, float *__restrict__ X) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * g.n_p) return;
+    const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
+    const int j = row_base + jr;   // index into the sorted events
+    const int a = ev_angle[j];
+    const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
+    const double e = (double)se[j] + g.e_c;
+    const int pix = st.p_pix[q];
+    const double cx = ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx, cy = ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx;
+    const double uq = -st.cs[2 * a + 1] * cx + st.cs[2 * a] * cy;
+    const double d = u - uq;
+    const double gk = exp(-d * d / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5);
+    float h = 0.0f;
+    if (gk > 0.0) {
+        const double beta0 = 2.0 * g.c2 * (g.e0 - g.e_c);
+        h = (float)(gk * (double)efac[j] * exp2((double)st.prim[(size_t)a * g.n_p + q] + beta0 * (double)se[j]));
+    }
+    H[(size_t)jr * g.n_qpad + q] = h;
+    float x[8];
+    features(g, st, q, a, u, e, (double)chord[j], x);
+    float *xo = X + (k - (int64_t)0) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xo[i] = x[i];
+}
+
+// Inference, step 3: add the network's scatter estimate.
+__global__ void k_surr_add(Geo g, int j0, int rows, const float *__restrict__ y, float *__restrict__ H) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)rows * g.n_p) return;
+    const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
+    const double s0 = 1.0 / (g.dx * g.sig_e);
+    const float s = (float)(s0 * fmax(exp((double)y[k]) - (double)kTargetFloor, 0.0));
+    H[(size_t)jr * g.n_qpad + q] += s;
+}
+
+// partial means with one pixel group: pmean[j] = sum_q f[real(j)][q] H[j][q]
+__global__ void k_row_mean(Geo g, const int *__restrict__ rrange, int n_real, int rows, const float *__restrict__ H,
+                           const float *__restrict__ f, float *__restrict__ pmean) {
+    const int j = blockIdx.x;
+    if (j >= rows) return;
+    int lo = 0, hi = n_real;   // realisation r with rrange[r] <= j < rrange[r+1]
+    while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (rrange[m] <= j) lo = m; else hi = m; }
+    const float *fr = f + (size_t)lo * g.n_qpad;
+    float s = 0.0f;
+    for (int q = threadIdx.x; q < g.n_p; q += 64) s = fmaf(fr[q], H[(size_t)j * g.n_qpad + q], s);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) pmean[j] = s;
+}
+
+hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel, const int32_t *angle,
+                             const float *u_bin, const float *energy, int64_t n, float *X, float *target,
+                             float *scatter, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs};
+    hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, g, s, t.p_pix + g.n_p,
+                       t.T, t.s_sorted, t.us_sorted, pixel, angle, u_bin, energy, n, X, target, scatter);
+    return hipGetLastError();
+}
+
+// System rows of one sub-iteration with the surrogate scatter term:
+// H[j][q] = primary(q; A_j) + S_net(q; A_j), and the partial means (one group).
+hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
+                          const float *se, const float *efac, const float *f, const int *rrange, int n_real,
+                          int row_base, int rows, float *H, float *pmean, float *chord, float *X, float *y,
+                          int64_t pair_cap, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs};
+    hipError_t e;
+    hipLaunchKernelGGL(k_event_chord, dim3((rows + 255) / 256), dim3(256), 0, st, g, s, ev_angle + row_base,
+                       su + row_base, rows, chord + row_base);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int rows_per = (int)std::max<int64_t>(1, pair_cap / g.n_p);
+    for (int j0 = 0; j0 < rows; j0 += rows_per) {
+        const int nr = std::min(rows_per, rows - j0);
+        const int64_t pairs = (int64_t)nr * g.n_p;
+        hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
+                           se, efac, chord, row_base, j0, nr, H, X);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        net_set_stream(net, st);
+        if ((e = net_forward(net, X, pairs, y)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, y, H);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_row_mean, dim3(rows), dim3(64), 0, st, g, rrange, n_real, rows, H, f, pmean);
+    return hipGetLastError();
+}
+
+}  // namespace lmo

@@ -69,6 +69,18 @@ __global__ void k_line_to_detector(Geo g, const float *__restrict__ mu, const in
     L[idx] = traverse(mu, g.nx, g.ny, g.dx, pix % g.nx, pix / g.nx, cs[2 * a], cs[2 * a + 1], 1e300);
 }
 
+// L^back_a(p): attenuation from the centre of p away from the detector (along -n_a)
+__global__ void k_line_away(Geo g, const float *__restrict__ mu, const int *__restrict__ p_pix,
+                            const double *__restrict__ cs, const double *__restrict__ L, float *__restrict__ Ldet,
+                            float *__restrict__ Lback) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.n_angles * g.n_p) return;
+    int a = idx / g.n_p, p = idx % g.n_p;
+    int pix = p_pix[p];
+    Lback[idx] = (float)traverse(mu, g.nx, g.ny, g.dx, pix % g.nx, pix / g.nx, -cs[2 * a], -cs[2 * a + 1], 1e300);
+    Ldet[idx] = (float)L[idx];
+}
+
 // Bt[s][q] = B(q, s) = mu(s) dx^2 exp(-l(q,s)) / (2 pi r): the probability that
 // a photon emitted at q interacts at the scatter point s (0 for s == q).
 __global__ void k_scatter_points(Geo g, const float *__restrict__ mu, const int *__restrict__ p_pix,
@@ -126,14 +138,17 @@ __global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__res
 __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
                              const double *__restrict__ L, const double *__restrict__ Bt,
                              const int *__restrict__ s_sorted, const double *__restrict__ D_sorted,
-                             float2 *__restrict__ T, double *__restrict__ sens_a) {
+                             float2 *__restrict__ T, double *__restrict__ sens_a, float *__restrict__ prim) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int a = blockIdx.y;
     if (q >= g.n_qpad) return;
-    float2 *Ta = T + (size_t)a * g.n_rpad * g.n_qpad + q;
-    for (int r = g.n_p; r < g.n_rpad; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
+    // T is null when only the sensitivity and the primary weights are wanted
+    float2 *Ta = T ? T + (size_t)a * g.n_rpad * g.n_qpad + q : nullptr;
+    if (Ta)
+        for (int r = g.n_p; r < g.n_rpad; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
     if (q >= g.n_p) {
-        for (int r = 0; r < g.n_p; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
+        if (Ta)
+            for (int r = 0; r < g.n_p; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
         sens_a[(size_t)a * g.n_qpad + q] = 0.0;
         return;
     }
@@ -172,7 +187,8 @@ __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double 
             double win = 0.5 * (erf((g.win_hi - ep) / s2) - erf((g.win_lo - ep) / s2));
             sens += w * D_sorted[o] * win;
         }
-        Ta[(size_t)r * g.n_qpad] = make_float2(alpha, beta);
+        if (s == q) prim[(size_t)a * g.n_p + q] = alpha;
+        if (Ta) Ta[(size_t)r * g.n_qpad] = make_float2(alpha, beta);
     }
     sens_a[(size_t)a * g.n_qpad + q] = sens;
 }
@@ -192,7 +208,8 @@ __global__ void k_sens_reduce(Geo g, const double *__restrict__ sens_a, float *_
     sens_all[q] = (float)(g.acq_time * tot);
 }
 
-hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes) {
+hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, hipStream_t st, std::string &err,
+                        int64_t &bytes) {
     hipError_t e;
     double *L = nullptr, *Bt = nullptr, *D_sorted = nullptr, *sens_a = nullptr;
     size_t nT = (size_t)g.n_angles * g.n_rpad * g.n_qpad;
@@ -210,16 +227,23 @@ hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &er
     CK(hipMalloc(&sens_a, sizeof(double) * g.n_angles * g.n_qpad), "alloc sens_a");
     CK(hipMalloc(&t.s_sorted, sizeof(int) * g.n_angles * g.n_p), "alloc ranks");
     CK(hipMalloc(&t.us_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc positions");
-    CK(hipMalloc(&t.T, sizeof(float2) * nT), "alloc path table");
+    if (store_paths) CK(hipMalloc(&t.T, sizeof(float2) * nT), "alloc path table");
+    CK(hipMalloc(&t.Ldet, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
+    CK(hipMalloc(&t.Lback, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
+    CK(hipMalloc(&t.prim, sizeof(float) * g.n_angles * g.n_p), "alloc primary weights");
     CK(hipMalloc(&t.sens, sizeof(float) * g.n_subsets * g.n_qpad), "alloc sens");
     CK(hipMalloc(&t.sens_all, sizeof(float) * g.n_qpad), "alloc sens_all");
-    bytes = (int64_t)(sizeof(float2) * nT + sizeof(int) * g.n_angles * g.n_p +
+    bytes = (int64_t)((store_paths ? sizeof(float2) * nT : 0) + 3 * sizeof(float) * g.n_angles * g.n_p +
+                      sizeof(int) * g.n_angles * g.n_p +
                       sizeof(double) * g.n_angles * g.n_p + sizeof(float) * (g.n_subsets + 1) * g.n_qpad);
 
     int na_np = g.n_angles * g.n_p;
     hipLaunchKernelGGL(k_line_to_detector, dim3((na_np + 255) / 256), dim3(256), 0, st, g, t.mu,
                        t.p_pix, t.cs, L);
     CK(hipGetLastError(), "line integrals");
+    hipLaunchKernelGGL(k_line_away, dim3((na_np + 255) / 256), dim3(256), 0, st, g, t.mu, t.p_pix, t.cs, L,
+                       t.Ldet, t.Lback);
+    CK(hipGetLastError(), "line integrals away");
     if (g.scatter) {
         hipLaunchKernelGGL(k_scatter_points, dim3((g.n_p + 255) / 256, g.n_p), dim3(256), 0, st, g,
                            t.mu, t.p_pix, Bt);
@@ -229,7 +253,7 @@ hipError_t build_tables(const Geo &g, Tables &t, hipStream_t st, std::string &er
                        t.cs, t.s_sorted, t.us_sorted, D_sorted);
     CK(hipGetLastError(), "rank");
     hipLaunchKernelGGL(k_path_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g,
-                       t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a);
+                       t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a, t.prim);
     CK(hipGetLastError(), "path table");
     hipLaunchKernelGGL(k_sens_reduce, dim3((g.n_qpad + 255) / 256), dim3(256), 0, st, g, sens_a,
                        t.sens, t.sens_all);

@@ -86,6 +86,15 @@ _sigs = {
     "lmosem_autotune": (_S, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
+    "lmosem_net_create": (_S, [_P, _P, ctypes.POINTER(_P)]),
+    "lmosem_net_destroy": (None, [_P]),
+    "lmosem_net_get_params": (_S, [_P, _P]),
+    "lmosem_net_forward": (_S, [_P, _P, ctypes.c_int64, _P]),
+    "lmosem_net_gradient": (_S, [_P, _P, _P, ctypes.c_int32, _P]),
+    "lmosem_net_train": (_S, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                              ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+    "lmosem_surrogate_samples": (_S, [_P, _P, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
+    "lmosem_set_surrogate": (_S, [_P, _P]),
     "lmosem_measure_alu_rates": (_S, [_P, ctypes.POINTER(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _sigs.items():
@@ -256,6 +265,91 @@ def lmosem_measure_alu_rates(stream: torch.cuda.Stream | None = None) -> dict:
     if s != OK:
         raise LmosemError(s, "ALU probe failed")
     return {"fma_per_s": out[0], "exp2_per_s": out[1], "term_per_s": out[2]}
+
+
+N_NET_PARAMS = 34305
+NET_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+
+
+def net_flatten(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], np.float32).ravel() for k in NET_KEYS])
+
+
+def net_unflatten(flat: np.ndarray) -> dict:
+    shapes = {"W1": (8, 128), "b1": (128,), "W2": (128, 128), "b2": (128,), "W3": (128, 128),
+              "b3": (128,), "W4": (128, 1), "b4": (1,)}
+    out, o = {}, 0
+    for k in NET_KEYS:
+        n = int(np.prod(shapes[k]))
+        out[k] = flat[o:o + n].reshape(shapes[k]).copy()
+        o += n
+    return out
+
+
+def _check_plain(status: int, what: str):
+    if status != OK:
+        raise LmosemError(status, what)
+
+
+def lmosem_net_create(params: dict, stream: torch.cuda.Stream | None = None):
+    flat = np.ascontiguousarray(net_flatten(params))
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    out = ctypes.c_void_p()
+    _check_plain(_lib.lmosem_net_create(flat.ctypes.data, ctypes.c_void_p(st), ctypes.byref(out)),
+                 "lmosem_net_create")
+    return out
+
+
+def lmosem_net_destroy(net):
+    _lib.lmosem_net_destroy(net)
+
+
+def lmosem_net_get_params(net) -> dict:
+    flat = np.empty(N_NET_PARAMS, np.float32)
+    _check_plain(_lib.lmosem_net_get_params(net, flat.ctypes.data), "lmosem_net_get_params")
+    return net_unflatten(flat)
+
+
+def lmosem_net_forward(net, X: torch.Tensor, y_out: torch.Tensor):
+    _check_plain(_lib.lmosem_net_forward(net, _dev_ptr(X, torch.float32, "X"), int(X.shape[0]),
+                                         _dev_ptr(y_out, torch.float32, "y")), "lmosem_net_forward")
+
+
+def lmosem_net_gradient(net, X: torch.Tensor, dy: torch.Tensor) -> dict:
+    g = np.empty(N_NET_PARAMS, np.float32)
+    _check_plain(_lib.lmosem_net_gradient(net, _dev_ptr(X, torch.float32, "X"),
+                                          _dev_ptr(dy, torch.float32, "dy"), int(X.shape[0]),
+                                          g.ctypes.data), "lmosem_net_gradient")
+    return net_unflatten(g)
+
+
+def lmosem_net_train(net, X: torch.Tensor, t: torch.Tensor, batch: int, epochs: int, lr: float,
+                     lr_decay: float = 1.0) -> np.ndarray:
+    loss = (ctypes.c_double * max(epochs, 1))()
+    _check_plain(_lib.lmosem_net_train(net, _dev_ptr(X, torch.float32, "X"), _dev_ptr(t, torch.float32, "t"),
+                                       int(X.shape[0]), int(batch), int(epochs), float(lr), float(lr_decay),
+                                       loss), "lmosem_net_train")
+    return np.ctypeslib.as_array(loss)[:epochs].copy()
+
+
+def lmosem_surrogate_samples(ctx, pixel: torch.Tensor, angle: torch.Tensor, u_bin: torch.Tensor,
+                             energy: torch.Tensor, want_scatter=False):
+    n = int(pixel.numel())
+    dev = pixel.device
+    X = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    sc = torch.empty(n, dtype=torch.float32, device=dev) if want_scatter else None
+    _check(ctx, _lib.lmosem_surrogate_samples(ctx, _dev_ptr(pixel, torch.int32, "pixel"),
+                                              _dev_ptr(angle, torch.int32, "angle"),
+                                              _dev_ptr(u_bin, torch.float32, "u_bin"),
+                                              _dev_ptr(energy, torch.float32, "energy"), n,
+                                              _dev_ptr(X, torch.float32, "X"), _dev_ptr(t, torch.float32, "t"),
+                                              _dev_ptr(sc, torch.float32, "scatter")))
+    return (X, t, sc) if want_scatter else (X, t)
+
+
+def lmosem_set_surrogate(ctx, net):
+    _check(ctx, _lib.lmosem_set_surrogate(ctx, net))
 
 
 class Context:

@@ -11,7 +11,8 @@ import subprocess
 
 import numpy as np
 
-from .phantoms import (Geometry, Workload, workload, phantom, seed_for,  # noqa: F401
+from .phantoms import (Geometry, Workload, workload, phantom, seed_for, mlp_init_params,  # noqa: F401,E501
+                       surrogate_sample_inputs,
                        batch_event_counts, striatal_masks, random_ellipse_map,
                        disk_phantom, brain_phantom, pixel_centres)
 

@@ -171,3 +171,42 @@ def batch_event_counts(w: Workload) -> np.ndarray:
     rng = np.random.default_rng(seed_for(w, 999_999))
     lo, hi = w.extra["min_events"], w.extra["max_events"]
     return np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), size=w.n_real))).astype(np.int64)
+
+
+# ---------------------------------------------------------------- surrogate
+MLP_SIZES = (8, 128, 128, 128, 1)
+
+
+def mlp_init_params(seed: int) -> dict:
+    """Seeded initial weights of the 8-128-128-128-1 scatter surrogate
+    (Glorot-uniform weights, zero biases); an input of training, shared by the
+    GPU trainer and the FP64 reference."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for i, (a, b) in enumerate(zip(MLP_SIZES[:-1], MLP_SIZES[1:]), start=1):
+        lim = math.sqrt(6.0 / (a + b))
+        p[f"W{i}"] = rng.uniform(-lim, lim, size=(a, b)).astype(np.float32)
+        p[f"b{i}"] = np.zeros(b, np.float32)
+    return p
+
+
+def surrogate_sample_inputs(g: Geometry, mu: np.ndarray, n: int, rng: np.random.Generator) -> dict:
+    """Seeded (pixel, angle, u_bin, energy) draws for surrogate training: the
+    pixel uniform on the mu > 0 support, the angle uniform, the position
+    uniform over the support's projection widened by 3 sigma_u and a pixel,
+    the energy uniform over the acceptance window."""
+    support = np.flatnonzero(np.asarray(mu).ravel() > 0).astype(np.int32)
+    pix = support[rng.integers(0, support.size, size=n)]
+    ang = rng.integers(0, g.n_angles, size=n).astype(np.int32)
+    X, Y = pixel_centres(g.nx, g.ny, g.pixel_cm)
+    xs, ys = X.ravel()[support], Y.ravel()[support]
+    th = g.angle0_rad + 2 * np.pi * np.arange(g.n_angles) / g.n_angles
+    u_all = -np.sin(th)[:, None] * xs[None, :] + np.cos(th)[:, None] * ys[None, :]
+    sig_u = g.fwhm_u_cm / (2 * math.sqrt(2 * math.log(2)))
+    pad = 3 * sig_u + g.pixel_cm
+    lo = (u_all.min(axis=1) - pad)[ang]
+    hi = (u_all.max(axis=1) + pad)[ang]
+    u = lo + (hi - lo) * rng.uniform(size=n)
+    ub = np.clip(u / g.bin_cm + 0.5 * g.n_bins, 0.0, np.nextafter(np.float32(g.n_bins), 0))
+    e = rng.uniform(g.win_lo_kev, g.win_hi_kev, size=n)
+    return {"pixel": pix, "angle": ang, "u_bin": ub.astype(np.float32), "energy": e.astype(np.float32)}

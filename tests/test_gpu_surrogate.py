@@ -1,0 +1,166 @@
+"""GPU tests of the learned scatter surrogate: the bf16 MFMA network against
+the FP64 reference with the same bf16 rounding points, Adam, the training
+samples against the oracle's exact scatter sum, and an end-to-end training
+run that must beat primary-only compensation."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+from oracle import mlp as M  # noqa: E402
+import synth  # noqa: E402
+
+
+def _lib():
+    from paper_2002_12471_amd import lmosem as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _params(seed):
+    p = synth.mlp_init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.normal(scale=0.1, size=p[k].shape).astype(np.float32)
+    return p
+
+
+def test_network_forward_matches_reference(dev):
+    L = _lib()
+    p = _params(5)
+    X = np.random.default_rng(1).normal(size=(1000, 8)).astype(np.float32)   # ragged: 1000 % 16 != 0
+    net = L.lmosem_net_create(p)
+    try:
+        y = torch.empty(1000, device=dev)
+        L.lmosem_net_forward(net, torch.as_tensor(X, device=dev), y)
+        torch.cuda.synchronize()
+        ref, _ = M.forward(p, X, bf16_round=True)
+        got = y.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+    finally:
+        L.lmosem_net_destroy(net)
+
+
+def test_network_gradient_matches_reference(dev):
+    L = _lib()
+    p = _params(6)
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(256, 8)).astype(np.float32)
+    dy = rng.normal(size=256).astype(np.float32) / 256
+    net = L.lmosem_net_create(p)
+    try:
+        g = L.lmosem_net_gradient(net, torch.as_tensor(X, device=dev), torch.as_tensor(dy, device=dev))
+    finally:
+        L.lmosem_net_destroy(net)
+    _, cache = M.forward(p, X, bf16_round=True)
+    ref = M.backward(p, cache, dy, bf16_round=True)
+    for k in ref:
+        err = np.linalg.norm(g[k].ravel() - ref[k].ravel()) / max(np.linalg.norm(ref[k]), 1e-12)
+        assert err <= 1e-2, (k, err)
+
+
+def test_adam_step_matches_reference(dev):
+    L = _lib()
+    p0 = _params(7)
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(128, 8)).astype(np.float32)
+    t = rng.normal(size=128).astype(np.float32)
+    net = L.lmosem_net_create(p0)
+    try:
+        Xd, td = torch.as_tensor(X, device=dev), torch.as_tensor(t, device=dev)
+        y = torch.empty(128, device=dev)
+        L.lmosem_net_forward(net, Xd, y)
+        dy = (2.0 * (y - td) / 128).contiguous()
+        g = L.lmosem_net_gradient(net, Xd, dy)
+        L.lmosem_net_train(net, Xd, td, batch=128, epochs=1, lr=1e-3)
+        p1 = L.lmosem_net_get_params(net)
+    finally:
+        L.lmosem_net_destroy(net)
+    zero = {k: np.zeros_like(v, dtype=np.float64) for k, v in p0.items()}
+    ref, _, _ = M.adam_step(p0, {k: g[k].astype(np.float64) for k in g}, zero, zero, 1, lr=1e-3)
+    for k in ref:
+        np.testing.assert_allclose(p1[k], ref[k], rtol=1e-5, atol=2e-8)
+
+
+def test_training_samples_match_oracle(dev):
+    L = _lib()
+    w = synth.workload("tiny")
+    g = w.geom.as_dict()
+    _, mu = synth.phantom(w)
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+    s = synth.surrogate_sample_inputs(w.geom, mu, 96, np.random.default_rng(11))
+    X, t, S = L.lmosem_surrogate_samples(ctx.handle, *[torch.as_tensor(s[k], device=dev)
+                                                       for k in ("pixel", "angle", "u_bin", "energy")],
+                                         want_scatter=True)
+    X, t, S = X.cpu().numpy(), t.cpu().numpy(), S.cpu().numpy()
+    m1 = O.OracleModel(g, mu)
+    m0 = O.OracleModel(g, mu, scatter=0)
+    for k in range(96):
+        pix, a = int(s["pixel"][k]), int(s["angle"][k])
+        u = float(m1.u_cm(s["u_bin"][k]))
+        e = float(s["energy"][k])
+        ref = m1.h(pix, a, u, e) - m0.h(pix, a, u, e)
+        assert S[k] == pytest.approx(ref, rel=1e-4, abs=1e-12 + 1e-6 * abs(ref)), k
+        np.testing.assert_allclose(X[k], O.surrogate_features(m1, pix, a, u, e), rtol=1e-5, atol=1e-6)
+        assert t[k] == pytest.approx(O.surrogate_target(ref, g), abs=2e-4)
+    ctx.close()
+
+
+def train_surrogate(L, dev, n_maps=48, per_map=8192, epochs=30, seed=404):
+    """Samples from random elliptical maps on the tiny grid, then Adam."""
+    w = synth.workload("surrogate_maps")
+    g = w.geom.as_dict()
+    rng = np.random.default_rng(seed)
+    Xs, ts = [], []
+    for _ in range(n_maps):
+        mu = synth.random_ellipse_map(w.geom, rng)
+        ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+        s = synth.surrogate_sample_inputs(w.geom, mu, per_map, rng)
+        X, t = L.lmosem_surrogate_samples(ctx.handle, *[torch.as_tensor(s[k], device=dev)
+                                                        for k in ("pixel", "angle", "u_bin", "energy")])
+        Xs.append(X)
+        ts.append(t)
+        ctx.close()
+    X = torch.cat(Xs)
+    t = torch.cat(ts)
+    perm = torch.as_tensor(rng.permutation(X.shape[0]), device=dev)
+    X, t = X[perm].contiguous(), t[perm].contiguous()
+    net = L.lmosem_net_create(synth.mlp_init_params(seed))
+    loss = L.lmosem_net_train(net, X, t, batch=2048, epochs=epochs, lr=2e-3, lr_decay=0.92)
+    return net, loss
+
+
+def test_trained_surrogate_beats_primary_only(dev):
+    L = _lib()
+    net, loss = train_surrogate(L, dev)
+    try:
+        assert loss[-1] < 0.2 * loss[0]
+        w = synth.workload("tiny")
+        g = w.geom.as_dict()
+        act, mu = synth.phantom(w)
+        ev = L.events_to_device(synth.workload_events(w), dev)
+        img = torch.as_tensor(act, device=dev)
+        mu_d = torch.as_tensor(mu, device=dev)
+        exact = L.Context(g, mu_d).forward(ev, img).double()
+        prim = L.Context(dict(g, scatter_model=0), mu_d).forward(ev, img).double()
+        sctx = L.Context(dict(g, scatter_model=2), mu_d)
+        L.lmosem_set_surrogate(sctx.handle, net)
+        surr = sctx.forward(ev, img).double()
+        err_s = float(((surr - exact).abs() / exact).mean())
+        err_p = float(((prim - exact).abs() / exact).mean())
+        print(f"mean relative event error: surrogate {err_s:.4f}, primary only {err_p:.4f}")
+        assert err_s < err_p / 3
+        # the surrogate context stores no path table
+        assert sctx.stats()["table_bytes"] < L.Context(g, mu_d).stats()["table_bytes"] / 10
+        sctx.close()
+    finally:
+        L.lmosem_net_destroy(net)
