@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "liblmosem_oracle.so")
 _lib = None
 
 __all__ = ["build", "OracleModel", "os_lm_mlem", "subset_update", "log_likelihood",
-           "surrogate_features", "surrogate_target",
+           "surrogate_features", "surrogate_target", "line_extent",
            "compton_energy", "kn_shape", "kn_total", "rho", "psi_bar", "resp_K", "resp_D",
            "resp_G", "resp_W", "line_integral", "circle_mean", "default_threads"]
 
@@ -256,25 +256,60 @@ class OracleModel:
 
 
 # ---------------------------------------------------------------- surrogate references
+def line_extent(mu: np.ndarray, dx: float, foot, nvec) -> tuple:
+    """Where the line foot + t nvec runs through pixels with mu > 0: the
+    smallest and largest t of those stretches, or None when it meets none.
+    Each stretch between consecutive crossings of the grid lines is assigned
+    to the pixel holding its midpoint."""
+    n = mu.shape[0]
+    half = 0.5 * n * dx
+    ts = []
+    for k in range(2):
+        if abs(nvec[k]) > 1e-15:
+            for m in range(n + 1):
+                ts.append(((m * dx - half) - foot[k]) / nvec[k])
+    ts = np.unique(np.array(ts))
+    t_in = t_out = None
+    for t0, t1 in zip(ts[:-1], ts[1:]):
+        if t1 - t0 < 1e-12:
+            continue
+        mid = foot + 0.5 * (t0 + t1) * np.asarray(nvec)
+        i, j = int(np.floor(mid[0] / dx + 0.5 * n)), int(np.floor(mid[1] / dx + 0.5 * n))
+        if 0 <= i < n and 0 <= j < n and mu[j, i] > 0:
+            t_in = t0 if t_in is None else t_in
+            t_out = t1
+    return None if t_in is None else (float(t_in), float(t_out))
+
+
 def surrogate_features(model: "OracleModel", pixel: int, a: int, u_cm: float, e_kev: float) -> np.ndarray:
-    """Inputs of the scatter surrogate for (pixel, angle, position, energy):
-    pixel position in the detector frame, offset of the event from it,
-    energy, attenuation from the pixel toward and away from the detector,
-    attenuation along the event's whole detector line, and mu at the pixel
-    (each with the fixed scale the network uses)."""
+    """Inputs of the scatter surrogate for (pixel, angle, position, energy),
+    each with the fixed scale the network uses: the event's offset from the
+    pixel's own detector position, the energy, where the event's detector
+    line enters and leaves the body relative to the pixel's depth, the line's
+    position-response-weighted attenuation sum_s mu(s) dx k(u - u_s) over all
+    pixels s (k the unnormalised truncated Gaussian position response),
+    the attenuation from the pixel toward and away from the detector, and mu
+    at the pixel."""
     g = model.geom
     n, dx = model.n, float(g["pixel_cm"])
     th = float(g.get("angle0_rad", 0.0)) + 2 * np.pi * a / int(g["n_angles"])
     nvec = np.array([np.cos(th), np.sin(th)])
     tvec = np.array([-np.sin(th), np.cos(th)])
-    c = np.array([((pixel % n) - (n - 1) / 2) * dx, ((pixel // n) - (n - 1) / 2) * dx])
+    idx = np.arange(n)
+    cx, cy = (idx - (n - 1) / 2) * dx, (idx - (n - 1) / 2) * dx
+    c = np.array([cx[pixel % n], cy[pixel // n]])
     far = 4.0 * n * dx
     uq, dq = float(c @ tvec), float(c @ nvec)
     to_det = line_integral(model.mu, dx, c, c + far * nvec)
     away = line_integral(model.mu, dx, c, c - far * nvec)
-    foot = u_cm * tvec
-    chord = line_integral(model.mu, dx, foot - far * nvec, foot + far * nvec)
-    return np.array([uq / 10, dq / 10, (u_cm - uq) / 2, (e_kev - 130) / 30, to_det, away, chord / 2,
+    ext = line_extent(model.mu, dx, u_cm * tvec, nvec)
+    d_in, d_out = (0.0, 0.0) if ext is None else (ext[0] - dq, ext[1] - dq)
+    sig_u = float(g["fwhm_u_cm"]) / (2 * np.sqrt(2 * np.log(2)))
+    ck = 0.0
+    for p in np.flatnonzero(model.mu.ravel() > 0):
+        us = float(np.array([cx[p % n], cy[p // n]]) @ tvec)
+        ck += model.mu.flat[p] * dx * max(np.exp(-(u_cm - us) ** 2 / (2 * sig_u ** 2)) - np.exp(-4.5), 0.0)
+    return np.array([(u_cm - uq) / 2, (e_kev - 130) / 30, d_in / 10, d_out / 10, ck / 2, to_det, away,
                      10 * model.mu.flat[pixel]])
 
 

@@ -54,7 +54,7 @@ struct lmosem_evset {
     double *ll = nullptr;     // [n_real]
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // one iteration without / with the log-likelihood
     int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
-    float *chord = nullptr;   // surrogate: per-event line attenuation [n]
+    float *col = nullptr;     // surrogate: per-event column features [n][4]
     float *X = nullptr;       // surrogate: network inputs [pair_cap][8]
     float *y = nullptr;       // surrogate: network outputs [pair_cap]
     size_t pb_chunks = 0;     // chunk rows allocated in pb
@@ -150,7 +150,7 @@ void free_set(lmosem_evset *s) {
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
-    hipFree(s->ll); hipFree(s->chord); hipFree(s->X); hipFree(s->y); hipFree(s->s.ang);
+    hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->y); hipFree(s->s.ang);
     delete s;
 }
 
@@ -171,7 +171,7 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
     AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
     AL(s->ll, sizeof(double) * s->s.n_real);
     if (c->surrogate) {
-        AL(s->chord, sizeof(float) * (size_t)std::max<int64_t>(s->s.n, 1));
+        AL(s->col, 4 * sizeof(float) * (size_t)std::max<int64_t>(s->s.n, 1));
         AL(s->X, sizeof(float) * 8 * (size_t)kPairCap);
         AL(s->y, sizeof(float) * (size_t)kPairCap);
     }
@@ -248,7 +248,7 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, hipStream_t st) {
     const int rows = v.row_off[i + 1] - v.row_off[i];
     if (c->surrogate)
         return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
-                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->chord, s->X, s->y, kPairCap, st);
+                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->col, s->X, s->y, kPairCap, st);
     return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
                           v.efac, s->f, s->H, s->pmean, v.row_off[i], rows, st);
 }
@@ -434,7 +434,7 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     CK(hipMemcpyAsync(c->t.cs, cs.data(), sizeof(double) * 2 * g.n_angles, hipMemcpyHostToDevice, c->st), "upload");
 #undef CK
     std::string err;
-    e = build_tables(g, c->t, !c->surrogate, c->st, err, c->table_bytes);
+    e = build_tables(g, c->t, !c->surrogate, c->surrogate, c->st, err, c->table_bytes);
     if (e != hipSuccess) {
         lmosem_destroy(c);
         return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE;
@@ -457,7 +457,7 @@ void lmosem_destroy(lmosem_ctx *c) {
     if (c->gst) hipStreamDestroy(c->gst);
     hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted);
     hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->t.Ldet); hipFree(c->t.Lback);
-    hipFree(c->t.prim); hipFree(c->bad_dev); hipFree(c->skipped_dev);
+    hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;
 }
 

@@ -64,11 +64,15 @@ struct Tables {
     float *Ldet = nullptr;       // [n_angles][n_p] attenuation from the pixel centre to the detector
     float *Lback = nullptr;      // [n_angles][n_p] attenuation from the pixel centre away from it
     float *prim = nullptr;       // [n_angles][n_p] alpha of each pixel's primary path
+    // learned-scatter contexts: exact near-field paths of each emission pixel
+    float2 *band = nullptr;      // [n_angles][band_w][n_qpad] (alpha, beta), rank band_lo + k
+    int *band_lo = nullptr;      // [n_angles][n_p] first rank of each pixel's band
+    int band_w = 0;              // longest band
 };
 
 // ---- table build (tables.hip) ----
-hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, hipStream_t st, std::string &err,
-                        int64_t &bytes);
+hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
+                        std::string &err, int64_t &bytes);
 
 // ---- event ingest (events.hip) ----
 struct EvSet;
@@ -126,7 +130,7 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
                              float *scatter, hipStream_t st);
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *chord, float *X, float *y,
+                          int row_base, int rows, float *H, float *pmean, float *col, float *X, float *y,
                           int64_t pair_cap, hipStream_t st);
 
 // ---- ALU rate probes (probe.hip) ----

@@ -1,16 +1,26 @@
 // Learned scatter surrogate: features, exact training targets, inference.
 //
 // The surrogate replaces the first-order scatter part of the system row,
-//     S(q; a, u, E) = sum_{s != q} w(q,s,a) K(u - u_s(a)) G(E; E'(q,s,a)),
-// by one network evaluation per (event, emission pixel); the primary term is
-// kept exact.  Inputs (all O(1)) for pixel q, angle a, event position u (cm)
-// and energy E (keV):
-//     u_q / 10, d_q / 10       q in the detector frame (u_q = c_q . t_a, d_q = c_q . n_a)
-//     (u - u_q) / 2            event position relative to q's primary position
-//     (E - 130) / 30           energy
-//     L_a(q), L_a^back(q)      attenuation from q toward and away from the detector
-//     C_a(u) / 2               attenuation along the whole detector line through u
-//     10 mu(q)                 attenuation coefficient at q
+//     S(q; a, u, E) = sum_{s != q} w(q,s,a) K(u - u_s) G(E; E'(q,s,a)),
+// by one network evaluation per (event, emission pixel), for the pairs whose
+// event lies outside q's own position response (|u - u_q| >= 3 sig_u).  Inside
+// it (the near field, where the scatter ends crowd around q and the sum is
+// dominated by a few nearby pixels) the sum is taken exactly from a banded
+// table of q's near path ends; the primary term is always exact.
+//
+// Network inputs (all O(1)) for pixel q, angle a, event position u (cm) and
+// energy E (keV), with q at (u_q, d_q) in the detector frame (d toward the
+// detector):
+//     (u - u_q) / 2               event position relative to q's own
+//     (E - 130) / 30              energy
+//     (d_in - d_q) / 10           where the event's detector line enters the
+//     (d_out - d_q) / 10            body (mu > 0) and leaves it, relative to q
+//                                   (both 0 when the line misses the body)
+//     ck / 2                      response-weighted attenuation of the line:
+//                                   sum_s mu(s) pixel_cm k(u - u_s)
+//     L_a(q), L_a^back(q)         attenuation from q toward and away from the detector
+//     10 mu(q)                    attenuation coefficient at q
+// with k(x) = exp(-x^2 / 2 sig_u^2) - e^-4.5 on |x| < 3 sig_u.
 // Target: y = ln(S / S0 + 1e-4) with S0 = 1 / (pixel_cm sigma_E); inverse
 // S = S0 max(e^y - 1e-4, 0).
 #include <hip/hip_runtime.h>
@@ -24,48 +34,9 @@ namespace lmo {
 
 constexpr float kTargetFloor = 1e-4f;
 
-// attenuation along the whole line {r : r . t = u} (both directions), by
-// boundary-to-boundary traversal from the line's entry into the grid
-__device__ double line_chord(const float *__restrict__ mu, const Geo &g, double nx, double ny, double u) {
-    const double tx = -ny, ty = nx;
-    const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dx;
-    const double px = u * tx, py = u * ty;          // foot of the line on the origin's normal
-    // slab clipping of p + t n against the grid box
-    double t0 = -1e300, t1 = 1e300;
-    const double p[2] = {px, py}, d[2] = {nx, ny}, h[2] = {hx, hy};
-    for (int k = 0; k < 2; ++k) {
-        if (fabs(d[k]) < 1e-300) {
-            if (p[k] <= -h[k] || p[k] >= h[k]) return 0.0;
-        } else {
-            double a = (-h[k] - p[k]) / d[k], b = (h[k] - p[k]) / d[k];
-            if (a > b) { double s = a; a = b; b = s; }
-            t0 = fmax(t0, a);
-            t1 = fmin(t1, b);
-        }
-    }
-    if (t1 <= t0) return 0.0;
-    double sum = 0.0, t = t0;
-    const double ex = px + t0 * nx, ey = py + t0 * ny;
-    // pixel of the entry point, nudged inside along the direction
-    const double eps = 1e-9 * g.dx;
-    int i = (int)floor((ex + eps * nx) / g.dx + 0.5 * g.nx);
-    int j = (int)floor((ey + eps * ny) / g.dx + 0.5 * g.ny);
-    i = min(max(i, 0), g.nx - 1);
-    j = min(max(j, 0), g.ny - 1);
-    const int sx = nx > 0 ? 1 : (nx < 0 ? -1 : 0), sy = ny > 0 ? 1 : (ny < 0 ? -1 : 0);
-    const double inf = 1e300;
-    double tmx = sx ? ((i + (sx > 0 ? 1 : 0) - 0.5 * g.nx) * g.dx - px) / nx : inf;
-    double tmy = sy ? ((j + (sy > 0 ? 1 : 0) - 0.5 * g.ny) * g.dx - py) / ny : inf;
-    const double tdx = sx ? g.dx / fabs(nx) : inf, tdy = sy ? g.dx / fabs(ny) : inf;
-    for (int guard = 0; guard < 4 * (g.nx + g.ny) + 8; ++guard) {
-        const double tn = fmin(fmin(tmx, tmy), t1);
-        if (tn > t) sum += (double)mu[j * g.nx + i] * (tn - t);
-        t = tn;
-        if (t >= t1) break;
-        if (tmx <= tmy) { i += sx; tmx += tdx; } else { j += sy; tmy += tdy; }
-        if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) break;
-    }
-    return sum;
+// unnormalised truncated position response k(x)
+__device__ inline double k_resp(const Geo &g, double x) {
+    return fmax(exp(-x * x / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5), 0.0);
 }
 
 struct SurrTables {
@@ -74,28 +45,96 @@ struct SurrTables {
     const int *p_pix;
     const float *mu;
     const double *cs;
+    const int *s_sorted;         // [n_angles][n_p]
+    const double *us_sorted;     // [n_angles][n_p]
 };
 
-__device__ inline void features(const Geo &g, const SurrTables &t, int q, int a, double u, double e,
-                                double chord, float *x) {
-    const int pix = t.p_pix[q];
+// Column features of the detector line {r : r . t_a = u}: its extent inside
+// the body along n_a, by boundary-to-boundary traversal from its entry into
+// the grid, and its response-weighted attenuation over the reachable ranks.
+// out = (d_in, d_out, ck, hit).
+__device__ float4 column(const Geo &g, const SurrTables &st, int a, double u) {
+    const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
+    const double tx = -ny, ty = nx;
+    double d_in = 0.0, d_out = 0.0;
+    bool hit = false;
+    const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dx;
+    const double px = u * tx, py = u * ty;          // foot of the line; d = parameter along n
+    double t0 = -1e300, t1 = 1e300;
+    bool miss = false;
+    const double p[2] = {px, py}, dir[2] = {nx, ny}, h[2] = {hx, hy};
+    for (int k = 0; k < 2; ++k) {
+        if (fabs(dir[k]) < 1e-300) {
+            if (p[k] <= -h[k] || p[k] >= h[k]) miss = true;
+        } else {
+            double lo = (-h[k] - p[k]) / dir[k], hi = (h[k] - p[k]) / dir[k];
+            if (lo > hi) { const double sw = lo; lo = hi; hi = sw; }
+            t0 = fmax(t0, lo);
+            t1 = fmin(t1, hi);
+        }
+    }
+    if (!miss && t1 > t0) {
+        double t = t0;
+        const double ex = px + t0 * nx, ey = py + t0 * ny;
+        const double eps = 1e-9 * g.dx;   // entry pixel, nudged inside along the direction
+        int i = (int)floor((ex + eps * nx) / g.dx + 0.5 * g.nx);
+        int j = (int)floor((ey + eps * ny) / g.dx + 0.5 * g.ny);
+        i = min(max(i, 0), g.nx - 1);
+        j = min(max(j, 0), g.ny - 1);
+        const int sx = nx > 0 ? 1 : (nx < 0 ? -1 : 0), sy = ny > 0 ? 1 : (ny < 0 ? -1 : 0);
+        const double inf = 1e300;
+        double tmx = sx ? ((i + (sx > 0 ? 1 : 0) - 0.5 * g.nx) * g.dx - px) / nx : inf;
+        double tmy = sy ? ((j + (sy > 0 ? 1 : 0) - 0.5 * g.ny) * g.dx - py) / ny : inf;
+        const double tdx = sx ? g.dx / fabs(nx) : inf, tdy = sy ? g.dx / fabs(ny) : inf;
+        for (int guard = 0; guard < 4 * (g.nx + g.ny) + 8; ++guard) {
+            const double tn = fmin(fmin(tmx, tmy), t1);
+            if (tn > t && st.mu[j * g.nx + i] > 0.0f) {
+                if (!hit) d_in = t;
+                d_out = tn;
+                hit = true;
+            }
+            t = tn;
+            if (t >= t1) break;
+            if (tmx <= tmy) { i += sx; tmx += tdx; } else { j += sy; tmy += tdy; }
+            if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) break;
+        }
+    }
+    const double *us = st.us_sorted + (size_t)a * g.n_p;
+    const double reach = 3.0 * g.sig_u;
+    int lo = 0, hi = g.n_p;   // first rank with us > u - reach
+    while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > u - reach) hi = m; else lo = m + 1; }
+    double ck = 0.0;
+    for (int r = lo; r < g.n_p && us[r] < u + reach; ++r)
+        ck += (double)st.mu[st.p_pix[st.s_sorted[(size_t)a * g.n_p + r]]] * g.dx * k_resp(g, u - us[r]);
+    return make_float4((float)d_in, (float)d_out, (float)ck, hit ? 1.0f : 0.0f);
+}
+
+__device__ inline void pixel_frame(const Geo &g, const SurrTables &st, int q, int a, double &uq, double &dq) {
+    const int pix = st.p_pix[q];
     const double cx = ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx, cy = ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx;
-    const double nx = t.cs[2 * a], ny = t.cs[2 * a + 1];
-    const double uq = -ny * cx + nx * cy, dq = nx * cx + ny * cy;
-    x[0] = (float)(uq / 10.0);
-    x[1] = (float)(dq / 10.0);
-    x[2] = (float)((u - uq) / 2.0);
-    x[3] = (float)((e - 130.0) / 30.0);
-    x[4] = t.Ldet[(size_t)a * g.n_p + q];
-    x[5] = t.Lback[(size_t)a * g.n_p + q];
-    x[6] = (float)(chord / 2.0);
-    x[7] = 10.0f * t.mu[pix];
+    const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
+    uq = cx * -ny + cy * nx;
+    dq = nx * cx + ny * cy;
+}
+
+__device__ inline void features(const Geo &g, const SurrTables &st, int q, int a, double u, double e, float4 col,
+                                float *x) {
+    double uq, dq;
+    pixel_frame(g, st, q, a, uq, dq);
+    const bool hit = col.w > 0.5f;
+    x[0] = (float)((u - uq) / 2.0);
+    x[1] = (float)((e - 130.0) / 30.0);
+    x[2] = hit ? (float)(((double)col.x - dq) / 10.0) : 0.0f;
+    x[3] = hit ? (float)(((double)col.y - dq) / 10.0) : 0.0f;
+    x[4] = col.z / 2.0f;
+    x[5] = st.Ldet[(size_t)a * g.n_p + q];
+    x[6] = st.Lback[(size_t)a * g.n_p + q];
+    x[7] = 10.0f * st.mu[st.p_pix[q]];
 }
 
 // Training samples: features and the exact target from the path table.
 __global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_of_pix,
-                               const float2 *__restrict__ T, const int *__restrict__ s_sorted,
-                               const double *__restrict__ us_sorted, const int32_t *__restrict__ pixel,
+                               const float2 *__restrict__ T, const int32_t *__restrict__ pixel,
                                const int32_t *__restrict__ angle, const float *__restrict__ u_bin,
                                const float *__restrict__ energy, int64_t n, float *__restrict__ X,
                                float *__restrict__ target, float *__restrict__ scatter) {
@@ -107,21 +146,20 @@ __global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_o
     const double e = (double)energy[k];
     const double ec = e - g.e_c;
     const double efac = exp2(-g.c2 * ec * ec) / g.zk;
-    const double *us = us_sorted + (size_t)a * g.n_p;
+    const double *us = st.us_sorted + (size_t)a * g.n_p;
     const double reach = 3.0 * g.sig_u;
     int lo = 0, hi = g.n_p;   // first rank with us > u - reach
     while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > u - reach) hi = m; else lo = m + 1; }
     double s = 0.0;
     for (int r = lo; r < g.n_p && us[r] < u + reach; ++r) {
-        if (s_sorted[(size_t)a * g.n_p + r] == q) continue;   // the primary path
-        const double d = u - us[r];
-        const double gk = exp(-d * d / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5);
+        if (st.s_sorted[(size_t)a * g.n_p + r] == q) continue;   // the primary path
+        const double gk = k_resp(g, u - us[r]);
         if (gk <= 0.0) continue;
         const float2 ab = T[((size_t)a * g.n_rpad + r) * g.n_qpad + q];
         s += gk * efac * exp2((double)ab.y * ec + (double)ab.x);
     }
     float x[8];
-    features(g, st, q, a, u, e, line_chord(st.mu, g, st.cs[2 * a], st.cs[2 * a + 1], u), x);
+    features(g, st, q, a, u, e, column(g, st, a, u), x);
 #pragma unroll
     for (int i = 0; i < 8; ++i) X[k * 8 + i] = x[i];
     const double s0 = 1.0 / (g.dx * g.sig_e);
@@ -129,52 +167,72 @@ __global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_o
     if (scatter) scatter[k] = (float)s;
 }
 
-// per event: attenuation along its detector line
-__global__ void k_event_chord(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
-                              int n, float *__restrict__ chord) {
+// per event: column features of its detector line
+__global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
+                               int n, float4 *__restrict__ col) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
-    chord[j] = (float)line_chord(st.mu, g, st.cs[2 * a], st.cs[2 * a + 1], u);
+    col[j] = column(g, st, ev_angle[j], u);
 }
 
 // Inference, step 1: for rows [j0, j0 + rows) of the sub-iteration and every
-// emission pixel q, the exact primary term into H and the network inputs.
-__global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
-                             const float *__restrict__ se, const float *__restrict__ efac,
-                             const float *__restrict__ chord, int row_base, int j0, int rows,
-                             float *__restrict__ H, float *__restrict__ X) {
+// emission pixel q, the exact primary and near-field scatter terms into H and
+// the network inputs.
+__global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ band, int band_w,
+                             const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
+                             const float *__restrict__ su, const float *__restrict__ se,
+                             const float *__restrict__ efac, const float4 *__restrict__ col, int row_base, int j0,
+                             int rows, float *__restrict__ H, float *__restrict__ X) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)rows * g.n_p) return;
     const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
     const int j = row_base + jr;   // index into the sorted events
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
-    const double e = (double)se[j] + g.e_c;
-    const int pix = st.p_pix[q];
-    const double cx = ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx, cy = ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx;
-    const double uq = -st.cs[2 * a + 1] * cx + st.cs[2 * a] * cy;
-    const double d = u - uq;
-    const double gk = exp(-d * d / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5);
-    float h = 0.0f;
+    const double et = (double)se[j];   // E - e_c
+    double uq, dq;
+    pixel_frame(g, st, q, a, uq, dq);
+    const double gk = k_resp(g, u - uq);
+    double h = 0.0;
     if (gk > 0.0) {
         const double beta0 = 2.0 * g.c2 * (g.e0 - g.e_c);
-        h = (float)(gk * (double)efac[j] * exp2((double)st.prim[(size_t)a * g.n_p + q] + beta0 * (double)se[j]));
+        h = gk * exp2((double)st.prim[(size_t)a * g.n_p + q] + beta0 * et);
+        // near field: the ends of q's band that the event reaches
+        const double *us = st.us_sorted + (size_t)a * g.n_p;
+        const double reach = 3.0 * g.sig_u;
+        const int lo = band_lo[(size_t)a * g.n_p + q];
+        const float2 *bq = band + (size_t)a * band_w * g.n_qpad + q;
+        for (int b = 0; b < band_w && lo + b < g.n_p; ++b) {
+            const double d = u - us[lo + b];
+            if (d <= -reach) break;
+            const double gs = k_resp(g, d);
+            if (gs <= 0.0) continue;
+            const float2 ab = bq[(size_t)b * g.n_qpad];
+            h += gs * exp2((double)ab.x + (double)ab.y * et);
+        }
+        h *= (double)efac[j];
     }
-    H[(size_t)jr * g.n_qpad + q] = h;
+    H[(size_t)jr * g.n_qpad + q] = (float)h;
     float x[8];
-    features(g, st, q, a, u, e, (double)chord[j], x);
-    float *xo = X + (k - (int64_t)0) * 8;
+    features(g, st, q, a, u, et + g.e_c, col[j], x);
+    float *xo = X + k * 8;
 #pragma unroll
     for (int i = 0; i < 8; ++i) xo[i] = x[i];
 }
 
-// Inference, step 3: add the network's scatter estimate.
-__global__ void k_surr_add(Geo g, int j0, int rows, const float *__restrict__ y, float *__restrict__ H) {
+// Inference, step 3: add the network's scatter estimate to the far-field pairs.
+__global__ void k_surr_add(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
+                           int row_base, int j0, int rows, const float *__restrict__ y, float *__restrict__ H) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)rows * g.n_p) return;
     const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
+    const int j = row_base + jr;
+    const int a = ev_angle[j];
+    const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
+    double uq, dq;
+    pixel_frame(g, st, q, a, uq, dq);
+    if (k_resp(g, u - uq) > 0.0) return;   // near field: exact
     const double s0 = 1.0 / (g.dx * g.sig_e);
     const float s = (float)(s0 * fmax(exp((double)y[k]) - (double)kTargetFloor, 0.0));
     H[(size_t)jr * g.n_qpad + q] += s;
@@ -199,9 +257,9 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted};
     hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, g, s, t.p_pix + g.n_p,
-                       t.T, t.s_sorted, t.us_sorted, pixel, angle, u_bin, energy, n, X, target, scatter);
+                       t.T, pixel, angle, u_bin, energy, n, X, target, scatter);
     return hipGetLastError();
 }
 
@@ -209,24 +267,26 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
 // H[j][q] = primary(q; A_j) + S_net(q; A_j), and the partial means (one group).
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *chord, float *X, float *y,
+                          int row_base, int rows, float *H, float *pmean, float *col, float *X, float *y,
                           int64_t pair_cap, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted};
+    float4 *col4 = reinterpret_cast<float4 *>(col);
     hipError_t e;
-    hipLaunchKernelGGL(k_event_chord, dim3((rows + 255) / 256), dim3(256), 0, st, g, s, ev_angle + row_base,
-                       su + row_base, rows, chord + row_base);
+    hipLaunchKernelGGL(k_event_column, dim3((rows + 255) / 256), dim3(256), 0, st, g, s, ev_angle + row_base,
+                       su + row_base, rows, col4 + row_base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rows_per = (int)std::max<int64_t>(1, pair_cap / g.n_p);
     for (int j0 = 0; j0 < rows; j0 += rows_per) {
         const int nr = std::min(rows_per, rows - j0);
         const int64_t pairs = (int64_t)nr * g.n_p;
-        hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
-                           se, efac, chord, row_base, j0, nr, H, X);
+        hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, t.band,
+                           t.band_w, t.band_lo, ev_angle, su, se, efac, col4, row_base, j0, nr, H, X);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         net_set_stream(net, st);
         if ((e = net_forward(net, X, pairs, y)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, y, H);
+        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
+                           row_base, j0, nr, y, H);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_row_mean, dim3(rows), dim3(64), 0, st, g, rrange, n_real, rows, H, f, pmean);

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <vector>
 
 #include "lmosem_int.h"
 
@@ -133,6 +134,34 @@ __global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__res
     D_sorted[o] = detector_mass(g, u);
 }
 
+// Weight w and end energy E' of the path from emission pixel q through path
+// end s at angle a (s == q: the primary path).
+struct PathW {
+    double w, ep;
+};
+
+__device__ inline PathW path_weight(const Geo &g, const int *__restrict__ p_pix, const double *__restrict__ L,
+                                    const double *__restrict__ Bt, double nx, double ny, int a, int q, int s) {
+    if (s == q) return {exp(-L[(size_t)a * g.n_p + q]), g.e0};
+    if (!g.scatter) return {0.0, g.e0};
+    const int pq = p_pix[q], ps = p_pix[s];
+    const int di = ps % g.nx - pq % g.nx, dj = ps / g.nx - pq / g.nx;
+    const double c = (di * nx + dj * ny) / sqrt((double)(di * di + dj * dj));
+    const double t = 1.0 + g.kappa * (1.0 - c);
+    const double P = 1.0 / t;
+    const double ep = g.e0 * P;
+    const double psi = P * P * (P + t - 1.0 + c * c);
+    const double rho = kn_total(ep) / g.sigma_kn_e0;
+    return {Bt[(size_t)s * g.n_p + q] * psi / g.psi_bar * exp(-rho * L[(size_t)a * g.n_p + s]), ep};
+}
+
+// (alpha, beta) code of a path weight; zero weight never contributes
+__device__ inline float2 path_code(const Geo &g, PathW p, double log2_gnorm) {
+    if (!(p.w > 0.0)) return make_float2(kNegHuge, 0.0f);
+    const double ec = p.ep - g.e_c;
+    return make_float2((float)(log2(p.w) + log2_gnorm - g.c2 * ec * ec), (float)(2.0 * g.c2 * ec));
+}
+
 // Path table and per-angle sensitivities.  One thread per (angle, emission
 // pixel q); it walks the path ends in rank order.
 __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
@@ -153,44 +182,68 @@ __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double 
         return;
     }
     const double nx = cs[2 * a], ny = cs[2 * a + 1];
-    const int pq = p_pix[q];
-    const int iq = pq % g.nx, jq = pq / g.nx;
     const double log2_gnorm = -log2(sqrt(2.0 * M_PI) * g.sig_e);
     const double s2 = M_SQRT2 * g.sig_e;
     double sens = 0.0;
     for (int r = 0; r < g.n_p; ++r) {
-        size_t o = (size_t)a * g.n_p + r;
-        int s = s_sorted[o];
-        double w, ep;
-        if (s == q) {
-            w = exp(-L[(size_t)a * g.n_p + q]);
-            ep = g.e0;
-        } else if (g.scatter) {
-            int ps = p_pix[s];
-            int di = ps % g.nx - iq, dj = ps / g.nx - jq;
-            double c = (di * nx + dj * ny) / sqrt((double)(di * di + dj * dj));
-            double t = 1.0 + g.kappa * (1.0 - c);
-            double P = 1.0 / t;
-            ep = g.e0 * P;
-            double psi = P * P * (P + t - 1.0 + c * c);
-            double rho = kn_total(ep) / g.sigma_kn_e0;
-            w = Bt[(size_t)s * g.n_p + q] * psi / g.psi_bar * exp(-rho * L[(size_t)a * g.n_p + s]);
-        } else {
-            w = 0.0;
-            ep = g.e0;
+        const size_t o = (size_t)a * g.n_p + r;
+        const int s = s_sorted[o];
+        const PathW pw = path_weight(g, p_pix, L, Bt, nx, ny, a, q, s);
+        const float2 code = path_code(g, pw, log2_gnorm);
+        if (pw.w > 0.0) {
+            const double win = 0.5 * (erf((g.win_hi - pw.ep) / s2) - erf((g.win_lo - pw.ep) / s2));
+            sens += pw.w * D_sorted[o] * win;
         }
-        float alpha = kNegHuge, beta = 0.0f;
-        if (w > 0.0) {
-            double ec = ep - g.e_c;
-            alpha = (float)(log2(w) + log2_gnorm - g.c2 * ec * ec);
-            beta = (float)(2.0 * g.c2 * ec);
-            double win = 0.5 * (erf((g.win_hi - ep) / s2) - erf((g.win_lo - ep) / s2));
-            sens += w * D_sorted[o] * win;
-        }
-        if (s == q) prim[(size_t)a * g.n_p + q] = alpha;
-        if (Ta) Ta[(size_t)r * g.n_qpad] = make_float2(alpha, beta);
+        if (s == q) prim[(size_t)a * g.n_p + q] = code.x;
+        if (Ta) Ta[(size_t)r * g.n_qpad] = code;
     }
     sens_a[(size_t)a * g.n_qpad + q] = sens;
+}
+
+// Near-field band of emission pixel q at angle a: the path ends whose detector
+// position lies within 6 sig_u of q's own (u_q), i.e. every end that an event
+// inside q's primary position response (|u - u_q| < 3 sig_u) can reach.  The
+// ends are a contiguous rank range [lo, hi).
+__global__ void k_band_range(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
+                             const double *__restrict__ us_sorted, int *__restrict__ band_lo,
+                             int *__restrict__ band_len) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (q >= g.n_p) return;
+    const int pix = p_pix[q];
+    const double uq = centre_x(g, pix) * -cs[2 * a + 1] + centre_y(g, pix) * cs[2 * a];
+    const double reach = 6.0 * g.sig_u;
+    const double *us = us_sorted + (size_t)a * g.n_p;
+    int lo = 0, hi = g.n_p;   // first rank with us > uq - reach
+    while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > uq - reach) hi = m; else lo = m + 1; }
+    int lo2 = lo, hi2 = g.n_p;   // first rank with us >= uq + reach
+    while (lo2 < hi2) { const int m = (lo2 + hi2) >> 1; if (us[m] >= uq + reach) hi2 = m; else lo2 = m + 1; }
+    band_lo[(size_t)a * g.n_p + q] = lo;
+    band_len[(size_t)a * g.n_p + q] = lo2 - lo;
+}
+
+// Near-field table band[a][k][q] = code of rank band_lo[a][q] + k (the
+// primary path s == q and slots past the band never contribute).
+__global__ void k_band_table(Geo g, int band_w, const int *__restrict__ p_pix, const double *__restrict__ cs,
+                             const double *__restrict__ L, const double *__restrict__ Bt,
+                             const int *__restrict__ s_sorted, const int *__restrict__ band_lo,
+                             const int *__restrict__ band_len, float2 *__restrict__ band) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (q >= g.n_qpad) return;
+    float2 *out = band + (size_t)a * band_w * g.n_qpad + q;
+    const int lo = q < g.n_p ? band_lo[(size_t)a * g.n_p + q] : 0;
+    const int len = q < g.n_p ? band_len[(size_t)a * g.n_p + q] : 0;
+    const double nx = cs[2 * a], ny = cs[2 * a + 1];
+    const double log2_gnorm = -log2(sqrt(2.0 * M_PI) * g.sig_e);
+    for (int k = 0; k < band_w; ++k) {
+        float2 code = make_float2(kNegHuge, 0.0f);
+        if (k < len) {
+            const int s = s_sorted[(size_t)a * g.n_p + lo + k];
+            if (s != q) code = path_code(g, path_weight(g, p_pix, L, Bt, nx, ny, a, q, s), log2_gnorm);
+        }
+        out[(size_t)k * g.n_qpad] = code;
+    }
 }
 
 // sens[i][q] = T sum_{a mod N_s == i} sens_a[a][q]; sens_all = sum over subsets.
@@ -208,16 +261,17 @@ __global__ void k_sens_reduce(Geo g, const double *__restrict__ sens_a, float *_
     sens_all[q] = (float)(g.acq_time * tot);
 }
 
-hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, hipStream_t st, std::string &err,
-                        int64_t &bytes) {
+hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
+                        std::string &err, int64_t &bytes) {
     hipError_t e;
     double *L = nullptr, *Bt = nullptr, *D_sorted = nullptr, *sens_a = nullptr;
+    int *band_len = nullptr;
     size_t nT = (size_t)g.n_angles * g.n_rpad * g.n_qpad;
     auto fail = [&](const char *what, hipError_t code) {
         char buf[256];
         snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(code));
         err = buf;
-        hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a);
+        hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
         return code;
     };
 #define CK(call, what) do { e = (call); if (e != hipSuccess) return fail(what, e); } while (0)
@@ -255,11 +309,28 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, hipStream_t s
     hipLaunchKernelGGL(k_path_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g,
                        t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a, t.prim);
     CK(hipGetLastError(), "path table");
+    if (store_band && g.scatter) {
+        CK(hipMalloc(&t.band_lo, sizeof(int) * g.n_angles * g.n_p), "alloc band ranges");
+        CK(hipMalloc(&band_len, sizeof(int) * g.n_angles * g.n_p), "alloc band ranges");
+        hipLaunchKernelGGL(k_band_range, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix, t.cs,
+                           t.us_sorted, t.band_lo, band_len);
+        CK(hipGetLastError(), "band ranges");
+        std::vector<int> len((size_t)g.n_angles * g.n_p);
+        CK(hipMemcpyAsync(len.data(), band_len, sizeof(int) * len.size(), hipMemcpyDeviceToHost, st), "band ranges");
+        CK(hipStreamSynchronize(st), "band ranges");
+        t.band_w = std::max(1, *std::max_element(len.begin(), len.end()));
+        const size_t nb = (size_t)g.n_angles * t.band_w * g.n_qpad;
+        CK(hipMalloc(&t.band, sizeof(float2) * nb), "alloc near-field table");
+        hipLaunchKernelGGL(k_band_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g, t.band_w,
+                           t.p_pix, t.cs, L, Bt, t.s_sorted, t.band_lo, band_len, t.band);
+        CK(hipGetLastError(), "near-field table");
+        bytes += (int64_t)(sizeof(float2) * nb + sizeof(int) * g.n_angles * g.n_p);
+    }
     hipLaunchKernelGGL(k_sens_reduce, dim3((g.n_qpad + 255) / 256), dim3(256), 0, st, g, sens_a,
                        t.sens, t.sens_all);
     CK(hipGetLastError(), "sensitivity");
     CK(hipStreamSynchronize(st), "table build");
-    hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a);
+    hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
 #undef CK
     return hipSuccess;
 }

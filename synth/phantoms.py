@@ -110,11 +110,12 @@ def striatal_masks(g: Geometry):
 
 def random_ellipse_map(g: Geometry, rng: np.random.Generator):
     """Random elliptical attenuation map for surrogate training: a body
-    ellipse plus 0-2 inserts, each with its own mu in [0.1, 0.3]/cm."""
+    ellipse (semi-axes 0.4-0.9 of the half field of view) plus 0-2 inserts,
+    each with its own mu in [0.1, 0.3]/cm."""
     X, Y = pixel_centres(g.nx, g.ny, g.pixel_cm)
     half = 0.5 * g.nx * g.pixel_cm
     mu = np.zeros_like(X)
-    body_a = rng.uniform(0.4, 0.75, size=2) * half
+    body_a = rng.uniform(0.4, 0.9, size=2) * half
     c = rng.uniform(-0.2, 0.2, size=2) * half
     body = _ellipse(X, Y, c[0], c[1], body_a[0], body_a[1], rng.uniform(0, 180))
     mu[body] = rng.uniform(0.1, 0.3)
@@ -192,11 +193,14 @@ def mlp_init_params(seed: int) -> dict:
 
 def surrogate_sample_inputs(g: Geometry, mu: np.ndarray, n: int, rng: np.random.Generator) -> dict:
     """Seeded (pixel, angle, u_bin, energy) draws for surrogate training: the
-    pixel uniform on the mu > 0 support, the angle uniform, the position
-    uniform over the support's projection widened by 3 sigma_u and a pixel,
-    the energy uniform over the acceptance window."""
+    pixel uniform on the mu > 0 support, the angle uniform, the energy uniform
+    over the acceptance window, and the position uniform over the support's
+    projection widened by 3 sigma_u and a pixel (kept on the detector), outside
+    the pixel's own position response |u - u_q| < 3 sigma_u (the near field,
+    which the network does not model)."""
     support = np.flatnonzero(np.asarray(mu).ravel() > 0).astype(np.int32)
-    pix = support[rng.integers(0, support.size, size=n)]
+    k = rng.integers(0, support.size, size=n)
+    pix = support[k]
     ang = rng.integers(0, g.n_angles, size=n).astype(np.int32)
     X, Y = pixel_centres(g.nx, g.ny, g.pixel_cm)
     xs, ys = X.ravel()[support], Y.ravel()[support]
@@ -204,9 +208,14 @@ def surrogate_sample_inputs(g: Geometry, mu: np.ndarray, n: int, rng: np.random.
     u_all = -np.sin(th)[:, None] * xs[None, :] + np.cos(th)[:, None] * ys[None, :]
     sig_u = g.fwhm_u_cm / (2 * math.sqrt(2 * math.log(2)))
     pad = 3 * sig_u + g.pixel_cm
-    lo = (u_all.min(axis=1) - pad)[ang]
-    hi = (u_all.max(axis=1) + pad)[ang]
-    u = lo + (hi - lo) * rng.uniform(size=n)
+    half_det = 0.5 * g.n_bins * g.bin_cm
+    lo = np.maximum((u_all.min(axis=1) - pad)[ang], -half_det)
+    hi = np.minimum((u_all.max(axis=1) + pad)[ang], half_det * (1 - 1e-6))
+    uq = u_all[ang, k]
+    gap_lo = np.clip(uq - 3 * sig_u, lo, hi)
+    gap_hi = np.clip(uq + 3 * sig_u, lo, hi)
+    u = lo + (hi - lo - (gap_hi - gap_lo)) * rng.uniform(size=n)
+    u = np.where(u >= gap_lo, u + (gap_hi - gap_lo), u)
     ub = np.clip(u / g.bin_cm + 0.5 * g.n_bins, 0.0, np.nextafter(np.float32(g.n_bins), 0))
     e = rng.uniform(g.win_lo_kev, g.win_hi_kev, size=n)
     return {"pixel": pix, "angle": ang, "u_bin": ub.astype(np.float32), "energy": e.astype(np.float32)}

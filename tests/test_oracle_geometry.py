@@ -146,3 +146,47 @@ def test_memoised_pair_paths_match_direct():
             assert m1.B(q, s) == pytest.approx(m0.B(q, s), rel=1e-14)
             assert m1.B(q, s) == pytest.approx(m1.B(s, q) * mu.flat[s] / mu.flat[q], rel=1e-12) \
                 if q != s else m1.B(q, s) == 0.0
+
+
+def test_line_extent_axis_aligned_matches_mask():
+    """A line along x through row j of a disk mask: the extent is the outer
+    boundary of that row's first and last mu > 0 pixel."""
+    n, dx = 16, 0.8
+    idx = (np.arange(n) - (n - 1) / 2) * dx
+    X, Y = np.meshgrid(idx, idx)
+    mu = np.where(X ** 2 + Y ** 2 <= (7 * dx) ** 2, 0.15, 0.0)
+    for j in (0, 1, 4, 8, 15):
+        u = (j - n / 2 + 0.37) * dx           # a y inside row j
+        ext = O.line_extent(mu, dx, np.array([0.0, u]), np.array([1.0, 0.0]))
+        cols = np.flatnonzero(mu[j] > 0)
+        if cols.size == 0:
+            assert ext is None
+            continue
+        assert ext[0] == pytest.approx((cols[0] - n / 2) * dx, abs=1e-12)
+        assert ext[1] == pytest.approx((cols[-1] + 1 - n / 2) * dx, abs=1e-12)
+
+
+def test_line_extent_oblique_matches_dense_sampling():
+    """Random map, oblique lines: the extent agrees with the first and last
+    mu > 0 hit of a dense walk along the line (to the walk's step)."""
+    rng = np.random.default_rng(9)
+    n, dx = 12, 0.5
+    mu = np.where(rng.uniform(size=(n, n)) < 0.4, 0.2, 0.0)
+    step = 2e-4
+    for _ in range(6):
+        th = rng.uniform(0, 2 * np.pi)
+        nvec, tvec = np.array([np.cos(th), np.sin(th)]), np.array([-np.sin(th), np.cos(th)])
+        foot = rng.uniform(-2.5, 2.5) * tvec
+        t = np.arange(-6.0, 6.0, step)
+        pts = foot[None, :] + t[:, None] * nvec[None, :]
+        i = np.floor(pts[:, 0] / dx + n / 2).astype(int)
+        j = np.floor(pts[:, 1] / dx + n / 2).astype(int)
+        ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+        hit = np.zeros(t.size, bool)
+        hit[ok] = mu[j[ok], i[ok]] > 0
+        ext = O.line_extent(mu, dx, foot, nvec)
+        if not hit.any():
+            assert ext is None
+            continue
+        assert ext[0] == pytest.approx(t[hit][0], abs=2 * step)
+        assert ext[1] == pytest.approx(t[hit][-1], abs=2 * step)
