@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "lmosem_int.h"
 
@@ -261,11 +262,185 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ---------------------------------------------------------------- fused inference
+// One kernel for the whole network.  The hidden units are the MFMA rows and
+// the samples the columns (Z^T[out][b] = sum_in W^T[out][in] H^T[in][b]), with
+// v_mfma_f32_16x16x32_bf16: a 16-row output block comes back with row
+// 4 (l/16) + v in register v of lane l (sample l % 16).  A 32-wide k-block over
+// inputs h0..h0+31 is permuted so that lane group g = l/16 holds inputs
+// {h0 + 4g .. +3} and {h0 + 16 + 4g .. +3} (the same permutation in the A and B
+// operands leaves the product unchanged): exactly the rows lane l holds of the
+// previous layer's output blocks 2 kb and 2 kb + 1, so activations stay in
+// registers from layer to layer.  The weights, pre-permuted into A-operand
+// lane order, the biases and the output row sit in LDS (75.8 KB: two
+// workgroups per CU); each wave takes 64 samples per step.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
+constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
+constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
+constexpr int kFB = 4 * kHid + 1;                // b1 b2 b3, w4 (bf16 values), b4
+constexpr int kFusedNB = 4;                      // 16-sample column blocks per wave
+constexpr int kFusedTile = 4 * 16 * kFusedNB;    // samples per workgroup step
+// gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
+// rewritten with one exp2 and one reciprocal
+constexpr float kGeluK0 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kGeluK1 = kGeluK0 * 0.044715f;
+
+__device__ __host__ inline int perm_k(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
+
+__global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__ fw, float *__restrict__ fb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < kFW1) {
+        const int i = idx & 7, lane = (idx >> 3) & 63, ob = idx >> 9;
+        const int in = perm_k(lane >> 4, i), out = 16 * ob + (lane & 15);
+        fw[idx] = in < kIn ? f2bf(p[kOffW1 + in * kHid + out]) : 0;
+    }
+    if (idx < 2 * kFW2) {
+        const int layer = idx / kFW2, r = idx % kFW2;
+        const int i = r & 7, lane = (r >> 3) & 63, kb = (r >> 9) & 3, ob = r >> 11;
+        const int in = 32 * kb + perm_k(lane >> 4, i), out = 16 * ob + (lane & 15);
+        fw[kFW1 + idx] = f2bf(p[(layer ? kOffW3 : kOffW2) + in * kHid + out]);
+    }
+    if (idx < kFB) {
+        float v;
+        if (idx < kHid) v = p[kOffB1 + idx];
+        else if (idx < 2 * kHid) v = p[kOffB2 + idx - kHid];
+        else if (idx < 3 * kHid) v = p[kOffB3 + idx - 2 * kHid];
+        else if (idx < 4 * kHid) v = bf2f(f2bf(p[kOffW4 + idx - 3 * kHid]));
+        else v = p[kOffB4];
+        fb[idx] = v;
+    }
+}
+
+__device__ inline float gelu_fast(float z) {
+    const float t = z * fmaf(kGeluK1, z * z, kGeluK0);
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-t));
+}
+
+// bias-initialised accumulators of output block ob for this lane's rows
+__device__ inline f32x4 bias4(const float *b, int ob, int g) {
+    return *reinterpret_cast<const f32x4 *>(b + 16 * ob + 4 * g);
+}
+
+// one 128 -> 128 layer with GELU, activations in and out as B operands
+__device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
+                                    bf16x8 (&act)[4][kFusedNB]) {
+    bf16x8 nxt[4][kFusedNB];
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) {
+        f32x4 acc[kFusedNB];
+        const f32x4 bv = bias4(b, ob, g);
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = bv;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = w[(ob * 4 + kb) * 64 + lane];
+#pragma unroll
+            for (int nb = 0; nb < kFusedNB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], acc[nb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[nb][v]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ fw, const float *__restrict__ fb,
+                                                 const float *__restrict__ X, int64_t n, float *__restrict__ y) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
+    __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(fw);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_w);
+        for (int i = threadIdx.x; i < kFWTotal / 8; i += 256) dst[i] = src[i];
+        for (int i = threadIdx.x; i < kFB; i += 256) s_b[i] = fb[i];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
+    const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
+    const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
+    const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // keep the weight reads inside the loop (hoisting them would need
+        // 288 registers)
+        __asm__ volatile("" ::: "memory");
+        const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
+        // layer 1: the inputs as B operands (lane groups 0 and 1 hold
+        // features 0..3 and 4..7; every other slot is zero)
+        bf16x8 act[4][kFusedNB];
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) {
+            const int64_t p = base + 16 * nb + r;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (g < 2 && p < n) v = *reinterpret_cast<const float4 *>(X + p * kIn + 4 * g);
+            const bf16x8 xin = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
+                                (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+            act[0][nb] = xin;
+        }
+        {
+            bf16x8 nxt[4][kFusedNB];
+#pragma unroll
+            for (int ob = 0; ob < 8; ++ob) {
+                const bf16x8 a = w1[ob * 64 + lane];
+                const f32x4 bv = bias4(s_b, ob, g);
+#pragma unroll
+                for (int nb = 0; nb < kFusedNB; ++nb) {
+                    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[0][nb], bv, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[v]);
+                }
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
+        }
+        hidden_layer(w2, s_b + kHid, lane, g, act);
+        hidden_layer(w3, s_b + 2 * kHid, lane, g, act);
+        // output row: this lane's 32 hidden units, then the sum over the 4 lane groups
+        float part[kFusedNB];
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) part[nb] = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float w4 = s_b[3 * kHid + 32 * kb + perm_k(g, i)];
+#pragma unroll
+                for (int nb = 0; nb < kFusedNB; ++nb) part[nb] = fmaf(w4, (float)act[kb][nb][i], part[nb]);
+            }
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) {
+            part[nb] += __shfl_xor(part[nb], 16, 64);
+            part[nb] += __shfl_xor(part[nb], 32, 64);
+            const int64_t p = base + 16 * nb + r;
+            if (g == 0 && p < n) y[p] = part[nb] + s_b[4 * kHid];
+        }
+    }
+}
+
+// per-epoch loss: fixed-order sum of the minibatch's partial sums
+__global__ void k_loss_add(const double *__restrict__ parts, int nparts, double *__restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += parts[i];
+    *loss += s;
+}
+
 // ---------------------------------------------------------------- host side
 struct Net {
     hipStream_t st = nullptr;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // [kNParams]
     NetBf16 nb{};
+    uint16_t *fw = nullptr;   // fused-inference weights [kFWTotal]
+    float *fb = nullptr;      // fused-inference biases and output row [kFB]
     int step = 0;
     // batch workspace
     int cap = 0;
@@ -322,10 +497,13 @@ hipError_t net_create(const float *params_host, hipStream_t st, Net **out) {
     if ((e = hipMalloc(&n->nb.w2, kHid * kHid * 2)) != hipSuccess) return bail(e);
     if ((e = hipMalloc(&n->nb.w3, kHid * kHid * 2)) != hipSuccess) return bail(e);
     if ((e = hipMalloc(&n->nb.w4, kHid * 2)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc(&n->fw, kFWTotal * 2)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc(&n->fb, kFB * 4)) != hipSuccess) return bail(e);
     if ((e = hipMemcpyAsync(n->p, params_host, kNParams * 4, hipMemcpyHostToDevice, st)) != hipSuccess) return bail(e);
     if ((e = hipMemsetAsync(n->m, 0, kNParams * 4, st)) != hipSuccess) return bail(e);
     if ((e = hipMemsetAsync(n->v, 0, kNParams * 4, st)) != hipSuccess) return bail(e);
     hipLaunchKernelGGL(k_pack, dim3((kHid * kHid + 255) / 256), dim3(256), 0, st, n->p, n->nb);
+    hipLaunchKernelGGL(k_pack_fused, dim3((2 * kFW2 + 255) / 256), dim3(256), 0, st, n->p, n->fw, n->fb);
     if ((e = hipGetLastError()) != hipSuccess) return bail(e);
     *out = n;
     return hipSuccess;
@@ -336,7 +514,7 @@ void net_destroy(Net *n) {
     free_ws(*n);
     hipFree(n->p); hipFree(n->g); hipFree(n->m); hipFree(n->v);
     hipFree(n->nb.w1t); hipFree(n->nb.w2t); hipFree(n->nb.w3t); hipFree(n->nb.w2); hipFree(n->nb.w3);
-    hipFree(n->nb.w4);
+    hipFree(n->nb.w4); hipFree(n->fw); hipFree(n->fb);
     delete n;
 }
 
@@ -388,25 +566,11 @@ static hipError_t backward_batch(Net &n, const float *dy, int nb) {
 }
 
 hipError_t net_forward(Net *n, const float *X, int64_t count, float *y) {
-    const int B = 8192;
-    hipError_t e = ensure_ws(*n, B);
-    for (int64_t s = 0; s < count && e == hipSuccess; s += B) {
-        const int nb = (int)std::min<int64_t>(B, count - s);
-        const int nb16 = (nb + 15) / 16 * 16;
-        // the tail reads up to 15 rows past the inputs' end only inside the
-        // padded workspace: copy the tail through it
-        if (nb16 != nb) {
-            float *tail = n->z3;   // [B][128] floats is larger than [16][8]
-            if ((e = hipMemsetAsync(tail, 0, (size_t)nb16 * kIn * 4, n->st)) != hipSuccess) break;
-            if ((e = hipMemcpyAsync(tail, X + s * kIn, (size_t)nb * kIn * 4, hipMemcpyDeviceToDevice, n->st)) != hipSuccess) break;
-            e = forward_batch(*n, tail, nb16, n->dy, false);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(y + s, n->dy, (size_t)nb * 4, hipMemcpyDeviceToDevice, n->st);
-        } else {
-            e = forward_batch(*n, X + s * kIn, nb, y + s, false);
-        }
-    }
-    return e;
+    if (count <= 0) return hipSuccess;
+    const int64_t tiles = (count + kFusedTile - 1) / kFusedTile;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2 * 256);   // two workgroups per CU
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, n->st, n->fw, n->fb, X, count, y);
+    return hipGetLastError();
 }
 
 hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host) {
@@ -424,15 +588,16 @@ hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, floa
 // the epoch's mean loss.
 hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
                      float lr_decay, double *loss_host) {
-    if (batch <= 0 || batch % 16 || count < batch) return hipErrorInvalidValue;
+    if (batch <= 0 || batch % 16 || count < batch || epochs < 0) return hipErrorInvalidValue;
     hipError_t e = ensure_ws(*n, batch);
     float *y = nullptr;
+    double *loss = nullptr;
     if (e == hipSuccess) e = hipMalloc(&y, (size_t)batch * 4);
+    if (e == hipSuccess) e = hipMalloc(&loss, sizeof(double) * std::max(epochs, 1));
+    if (e == hipSuccess) e = hipMemsetAsync(loss, 0, sizeof(double) * std::max(epochs, 1), n->st);
     const int64_t n_batches = count / batch;
     const int nparts = (batch + 255) / 256;
-    std::vector<double> parts(nparts);
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
-        double tot = 0.0;
         for (int64_t bi = 0; bi < n_batches && e == hipSuccess; ++bi) {
             const float *xb = X + bi * batch * kIn;
             const float *tb = t + bi * batch;
@@ -440,25 +605,29 @@ hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int 
             if (e != hipSuccess) break;
             hipLaunchKernelGGL(k_mse, dim3(nparts), dim3(256), 0, n->st, y, tb, batch, 1.0f / batch, n->dy,
                                n->loss_part);
+            hipLaunchKernelGGL(k_loss_add, dim3(1), dim3(64), 0, n->st, n->loss_part, nparts, loss + ep);
             if ((e = backward_batch(*n, n->dy, batch)) != hipSuccess) break;
             ++n->step;
             const float c1 = 1.0f - powf(0.9f, (float)n->step), c2 = 1.0f - powf(0.999f, (float)n->step);
             hipLaunchKernelGGL(k_adam, dim3(blocks(kNParams)), dim3(256), 0, n->st, n->p, n->g, n->m, n->v, kNParams,
                                lr, 0.9f, 0.999f, 1e-8f, c1, c2);
             hipLaunchKernelGGL(k_pack, dim3((kHid * kHid + 255) / 256), dim3(256), 0, n->st, n->p, n->nb);
-            if ((e = hipGetLastError()) != hipSuccess) break;
-            if (loss_host) {
-                if ((e = hipMemcpyAsync(parts.data(), n->loss_part, nparts * 8, hipMemcpyDeviceToHost, n->st)) != hipSuccess)
-                    break;
-                if ((e = hipStreamSynchronize(n->st)) != hipSuccess) break;
-                for (double d : parts) tot += d;
-            }
+            e = hipGetLastError();
         }
-        if (loss_host) loss_host[ep] = tot / ((double)n_batches * batch);
         lr *= lr_decay;
     }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pack_fused, dim3((2 * kFW2 + 255) / 256), dim3(256), 0, n->st, n->p, n->fw, n->fb);
+        e = hipGetLastError();
+    }
+    std::vector<double> tot(std::max(epochs, 1), 0.0);
+    if (e == hipSuccess && epochs > 0)
+        e = hipMemcpyAsync(tot.data(), loss, sizeof(double) * epochs, hipMemcpyDeviceToHost, n->st);
     if (e == hipSuccess) e = hipStreamSynchronize(n->st);
+    if (e == hipSuccess && loss_host)
+        for (int ep = 0; ep < epochs; ++ep) loss_host[ep] = tot[ep] / ((double)n_batches * batch);
     hipFree(y);
+    hipFree(loss);
     return e;
 }
 
