@@ -54,8 +54,9 @@ struct lmosem_evset {
     double *ll = nullptr;     // [n_real]
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // one iteration without / with the log-likelihood
     int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
-    float *col = nullptr;     // surrogate: per-event column features [n][4]
+    float *col = nullptr;     // surrogate: per-sub-iteration event column features [max_rows][4] + ranks [max_rows][2]
     float *X = nullptr;       // surrogate: network inputs [pair_cap][8]
+    uint8_t *near = nullptr;  // surrogate: near-field flag per pair [pair_cap]
     float *y = nullptr;       // surrogate: network outputs [pair_cap]
     size_t pb_chunks = 0;     // chunk rows allocated in pb
 };
@@ -150,7 +151,7 @@ void free_set(lmosem_evset *s) {
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
-    hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->y); hipFree(s->s.ang);
+    hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->near); hipFree(s->y); hipFree(s->s.ang);
     delete s;
 }
 
@@ -171,9 +172,10 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
     AL(s->f, sizeof(float) * (size_t)s->s.n_real * g.n_qpad);
     AL(s->ll, sizeof(double) * s->s.n_real);
     if (c->surrogate) {
-        AL(s->col, 4 * sizeof(float) * (size_t)std::max<int64_t>(s->s.n, 1));
+        AL(s->col, 6 * sizeof(float) * (size_t)std::max(s->s.max_rows, 1));
         AL(s->X, sizeof(float) * 8 * (size_t)kPairCap);
         AL(s->y, sizeof(float) * (size_t)kPairCap);
+        AL(s->near, (size_t)kPairCap);
     }
 #undef AL
     return LMOSEM_OK;
@@ -248,7 +250,7 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, hipStream_t st) {
     const int rows = v.row_off[i + 1] - v.row_off[i];
     if (c->surrogate)
         return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
-                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->col, s->X, s->y, kPairCap, st);
+                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st);
     return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
                           v.efac, s->f, s->H, s->pmean, v.row_off[i], rows, st);
 }
@@ -455,7 +457,7 @@ void lmosem_destroy(lmosem_ctx *c) {
     if (c->g_in) hipEventDestroy(c->g_in);
     if (c->g_out) hipEventDestroy(c->g_out);
     if (c->gst) hipStreamDestroy(c->gst);
-    hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted);
+    hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted); hipFree(c->t.mu_sorted);
     hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->t.Ldet); hipFree(c->t.Lback);
     hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;

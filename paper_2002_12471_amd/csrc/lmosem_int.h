@@ -58,6 +58,7 @@ struct Tables {
     double *cs = nullptr;        // [n_angles][2] cos, sin of theta_a
     int *s_sorted = nullptr;     // [n_angles][n_p] path-end support index by rank
     double *us_sorted = nullptr; // [n_angles][n_p] detector position of each rank (cm)
+    float *mu_sorted = nullptr;  // [n_angles][n_p] mu at each rank's pixel
     float2 *T = nullptr;         // [n_angles][n_rpad][n_qpad] (alpha, beta) per path
     float *sens = nullptr;       // [n_subsets][n_qpad]
     float *sens_all = nullptr;   // [n_qpad]
@@ -124,13 +125,13 @@ hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, floa
 hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
                      float lr_decay, double *loss_host);
 hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *C, int ldc, int M, int N,
-                   int K, bool accumulate, hipStream_t st);
+                   int K, bool accumulate, hipStream_t st, float *split_ws = nullptr);
 hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel, const int32_t *angle,
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st);
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *col, float *X, float *y,
+                          int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X, float *y,
                           int64_t pair_cap, hipStream_t st);
 
 // ---- ALU rate probes (probe.hip) ----

@@ -44,11 +44,15 @@ __device__ inline float gelu_grad(float x) {
 }
 
 // C[M][N] (+)= A[M][K] . Bt[N][K]^T; M, N, K multiples of 16, lda/ldb multiples of 4.
-// 64x64 block per workgroup, 32x32 per wave (2x2 MFMA tiles).
+// 64x64 block per workgroup, 32x32 per wave (2x2 MFMA tiles).  With split K,
+// blockIdx.z takes k in [z k_slice, (z+1) k_slice) and writes its partial
+// product to C + z c_stride.
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
                                                  const uint16_t *__restrict__ Bt, int ldb,
                                                  float *__restrict__ C, int ldc, int M, int N, int K,
-                                                 int accumulate) {
+                                                 int accumulate, int k_slice, size_t c_stride) {
+    const int kz0 = blockIdx.z * k_slice, kz1 = min(K, kz0 + k_slice);
+    C += blockIdx.z * c_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m_base = blockIdx.y * 64 + (wave >> 1) * 32;
     const int n_base = blockIdx.x * 64 + (wave & 1) * 32;
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x4 zero = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kz0; k0 < kz1; k0 += 16) {
         bf16x4 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -89,11 +93,39 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
             }
 }
 
+// C[m][n] = sum over the S partial products (fixed order)
+__global__ void k_sum_slices(const float *__restrict__ part, int S, int M, int N, float *__restrict__ C, int ldc) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    float s = 0.0f;
+    for (int z = 0; z < S; ++z) s += part[(size_t)z * M * N + idx];
+    C[(size_t)(idx / N) * ldc + idx % N] = s;
+}
+
+constexpr int kSplitMax = 32;   // partial products per split-K product (workspace slices)
+
+// Products with few output blocks and a long K (the weight gradients, K = the
+// batch) are split over K into up to kSplitMax slices of at least 256 in
+// split_ws ([kSplitMax][M][N]) and summed in a fixed order.
 hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *C, int ldc, int M, int N,
-                   int K, bool accumulate, hipStream_t st) {
+                   int K, bool accumulate, hipStream_t st, float *split_ws) {
     if (M % 16 || N % 16 || K % 16 || lda % 4 || ldb % 4) return hipErrorInvalidValue;
     dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, A, lda, Bt, ldb, C, ldc, M, N, K, accumulate ? 1 : 0);
+    const int blocks_mn = (int)(grid.x * grid.y);
+    int S = 1;
+    if (split_ws && !accumulate && M * N <= 128 * 128 && K >= 512)
+        S = std::min(kSplitMax, std::max(1, std::min(K / 256, 256 / blocks_mn)));
+    if (S <= 1) {
+        hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, A, lda, Bt, ldb, C, ldc, M, N, K, accumulate ? 1 : 0,
+                           K, (size_t)0);
+        return hipGetLastError();
+    }
+    const int k_slice = ((K + S - 1) / S + 15) / 16 * 16;
+    S = (K + k_slice - 1) / k_slice;
+    grid.z = (unsigned)S;
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, A, lda, Bt, ldb, split_ws, N, M, N, K, 0, k_slice,
+                       (size_t)M * N);
+    hipLaunchKernelGGL(k_sum_slices, dim3((M * N + 255) / 256), dim3(256), 0, st, split_ws, S, M, N, C, ldc);
     return hipGetLastError();
 }
 
@@ -273,13 +305,14 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 // previous layer's output blocks 2 kb and 2 kb + 1, so activations stay in
 // registers from layer to layer.  The weights, pre-permuted into A-operand
 // lane order, the biases and the output row sit in LDS (75.8 KB: two
-// workgroups per CU); each wave takes 64 samples per step.
+// workgroups per CU); each wave takes 32 samples per step (146 VGPRs, so
+// two waves per SIMD).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
 constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
 constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
 constexpr int kFB = 4 * kHid + 1;                // b1 b2 b3, w4 (bf16 values), b4
-constexpr int kFusedNB = 4;                      // 16-sample column blocks per wave
+constexpr int kFusedNB = 2;                      // 16-sample column blocks per wave
 constexpr int kFusedTile = 4 * 16 * kFusedNB;    // samples per workgroup step
 // gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
 // rewritten with one exp2 and one reciprocal
@@ -448,6 +481,7 @@ struct Net {
     uint16_t *h1t = nullptr, *h2t = nullptr, *h3t = nullptr;
     uint16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d1t = nullptr, *d2t = nullptr, *d3t = nullptr;
     float *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *dh = nullptr, *dy = nullptr, *gw1 = nullptr;
+    float *split = nullptr;   // split-K partial products [kSplitMax][128][128]
     double *loss_part = nullptr;
 };
 
@@ -455,11 +489,11 @@ static void free_ws(Net &n) {
     for (void *q : {(void *)n.xb, (void *)n.xt, (void *)n.h1, (void *)n.h2, (void *)n.h3, (void *)n.h1t,
                     (void *)n.h2t, (void *)n.h3t, (void *)n.d1, (void *)n.d2, (void *)n.d3, (void *)n.d1t,
                     (void *)n.d2t, (void *)n.d3t, (void *)n.z1, (void *)n.z2, (void *)n.z3, (void *)n.dh,
-                    (void *)n.dy, (void *)n.gw1, (void *)n.loss_part})
+                    (void *)n.dy, (void *)n.gw1, (void *)n.split, (void *)n.loss_part})
         hipFree(q);
     n.xb = n.xt = n.h1 = n.h2 = n.h3 = n.h1t = n.h2t = n.h3t = nullptr;
     n.d1 = n.d2 = n.d3 = n.d1t = n.d2t = n.d3t = nullptr;
-    n.z1 = n.z2 = n.z3 = n.dh = n.dy = n.gw1 = nullptr;
+    n.z1 = n.z2 = n.z3 = n.dh = n.dy = n.gw1 = n.split = nullptr;
     n.loss_part = nullptr;
     n.cap = 0;
 }
@@ -477,6 +511,7 @@ static hipError_t ensure_ws(Net &n, int cap) {
     A(n.d1t, c * kHid * 2) A(n.d2t, c * kHid * 2) A(n.d3t, c * kHid * 2)
     A(n.z1, c * kHid * 4) A(n.z2, c * kHid * 4) A(n.z3, c * kHid * 4) A(n.dh, c * kHid * 4)
     A(n.dy, c * 4) A(n.gw1, kInPad * kHid * 4) A(n.loss_part, (c / 256 + 2) * 8)
+    A(n.split, (size_t)kSplitMax * kHid * kHid * 4)
 #undef A
     n.cap = cap;
     return hipSuccess;
@@ -553,13 +588,15 @@ static hipError_t backward_batch(Net &n, const float *dy, int nb) {
     const size_t nh = (size_t)nb * kHid;
     hipLaunchKernelGGL(k_out_back, dim3(blocks(nh)), dim3(256), 0, st, dy, n.nb.w4, n.z3, nb, n.d3, n.d3t);
     // dW3[in][out] = h2t . d3t ; dh2 = d3 . W3
-    if ((e = gemm_nt(n.h2t, nb, n.d3t, nb, n.g + kOffW3, kHid, kHid, kHid, nb, false, st)) != hipSuccess) return e;
+    if ((e = gemm_nt(n.h2t, nb, n.d3t, nb, n.g + kOffW3, kHid, kHid, kHid, nb, false, st, n.split)) != hipSuccess)
+        return e;
     if ((e = gemm_nt(n.d3, kHid, n.nb.w3, kHid, n.dh, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks(nh)), dim3(256), 0, st, n.dh, n.z2, nb, n.d2, n.d2t);
-    if ((e = gemm_nt(n.h1t, nb, n.d2t, nb, n.g + kOffW2, kHid, kHid, kHid, nb, false, st)) != hipSuccess) return e;
+    if ((e = gemm_nt(n.h1t, nb, n.d2t, nb, n.g + kOffW2, kHid, kHid, kHid, nb, false, st, n.split)) != hipSuccess)
+        return e;
     if ((e = gemm_nt(n.d2, kHid, n.nb.w2, kHid, n.dh, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks(nh)), dim3(256), 0, st, n.dh, n.z1, nb, n.d1, n.d1t);
-    if ((e = gemm_nt(n.xt, nb, n.d1t, nb, n.gw1, kHid, kInPad, kHid, nb, false, st)) != hipSuccess) return e;
+    if ((e = gemm_nt(n.xt, nb, n.d1t, nb, n.gw1, kHid, kInPad, kHid, nb, false, st, n.split)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_copy_w1_grad, dim3(blocks(kIn * kHid)), dim3(256), 0, st, n.gw1, n.g);
     hipLaunchKernelGGL(k_bias_grads, dim3(4 * kHid + 1), dim3(256), 0, st, n.d1t, n.d2t, n.d3t, n.h3t, dy, nb, n.g);
     return hipGetLastError();

@@ -39,6 +39,12 @@ __device__ inline double k_resp(const Geo &g, double x) {
     return fmax(exp(-x * x / (2.0 * g.sig_u * g.sig_u)) - exp(-4.5), 0.0);
 }
 
+// FP32 position response (the exact forward kernel evaluates it in
+// FP32 too)
+__device__ inline float k_resp_f(float d, float inv2s2) {
+    return fmaxf(__expf(-d * d * inv2s2) - 0.011108996538242306f, 0.0f);   // e^-4.5
+}
+
 struct SurrTables {
     const float *Ldet, *Lback;   // [n_angles][n_p]
     const float *prim;           // [n_angles][n_p] alpha of the primary path
@@ -47,13 +53,14 @@ struct SurrTables {
     const double *cs;
     const int *s_sorted;         // [n_angles][n_p]
     const double *us_sorted;     // [n_angles][n_p]
+    const float *mu_sorted;      // [n_angles][n_p]
 };
 
 // Column features of the detector line {r : r . t_a = u}: its extent inside
 // the body along n_a, by boundary-to-boundary traversal from its entry into
 // the grid, and its response-weighted attenuation over the reachable ranks.
 // out = (d_in, d_out, ck, hit).
-__device__ float4 column(const Geo &g, const SurrTables &st, int a, double u) {
+__device__ float4 column(const Geo &g, const SurrTables &st, int a, double u, int2 *reach_ranks = nullptr) {
     const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
     const double tx = -ny, ty = nx;
     double d_in = 0.0, d_out = 0.0;
@@ -100,13 +107,17 @@ __device__ float4 column(const Geo &g, const SurrTables &st, int a, double u) {
         }
     }
     const double *us = st.us_sorted + (size_t)a * g.n_p;
+    const float *mus = st.mu_sorted + (size_t)a * g.n_p;
     const double reach = 3.0 * g.sig_u;
     int lo = 0, hi = g.n_p;   // first rank with us > u - reach
     while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > u - reach) hi = m; else lo = m + 1; }
-    double ck = 0.0;
-    for (int r = lo; r < g.n_p && us[r] < u + reach; ++r)
-        ck += (double)st.mu[st.p_pix[st.s_sorted[(size_t)a * g.n_p + r]]] * g.dx * k_resp(g, u - us[r]);
-    return make_float4((float)d_in, (float)d_out, (float)ck, hit ? 1.0f : 0.0f);
+    int lo2 = lo, hi2 = g.n_p;   // first rank with us >= u + reach
+    while (lo2 < hi2) { const int m = (lo2 + hi2) >> 1; if (us[m] >= u + reach) hi2 = m; else lo2 = m + 1; }
+    const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
+    float ck = 0.0f;
+    for (int r = lo; r < lo2; ++r) ck = fmaf(mus[r], k_resp_f((float)(u - us[r]), inv2s2), ck);
+    if (reach_ranks) *reach_ranks = make_int2(lo, lo2);
+    return make_float4((float)d_in, (float)d_out, ck * (float)g.dx, hit ? 1.0f : 0.0f);
 }
 
 __device__ inline void pixel_frame(const Geo &g, const SurrTables &st, int q, int a, double &uq, double &dq) {
@@ -167,75 +178,73 @@ __global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_o
     if (scatter) scatter[k] = (float)s;
 }
 
-// per event: column features of its detector line
+// per event: column features of its detector line and the rank range
+// [r0, r1) of path ends its position response reaches
 __global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
-                               int n, float4 *__restrict__ col) {
+                               int n, float4 *__restrict__ col, int2 *__restrict__ rr) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
-    col[j] = column(g, st, ev_angle[j], u);
+    int2 r;
+    col[j] = column(g, st, ev_angle[j], u, &r);
+    rr[j] = r;
 }
 
 // Inference, step 1: for rows [j0, j0 + rows) of the sub-iteration and every
-// emission pixel q, the exact primary and near-field scatter terms into H and
-// the network inputs.
+// emission pixel q, the exact primary and near-field scatter terms into H, the
+// near-field flag (|u - u_q| < 3 sig_u) and the network inputs.
 __global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ band, int band_w,
                              const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
                              const float *__restrict__ su, const float *__restrict__ se,
-                             const float *__restrict__ efac, const float4 *__restrict__ col, int row_base, int j0,
-                             int rows, float *__restrict__ H, float *__restrict__ X) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)rows * g.n_p) return;
-    const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
+                             const float *__restrict__ efac, const float4 *__restrict__ col,
+                             const int2 *__restrict__ rr, int row_base, int j0, int rows, float *__restrict__ H,
+                             uint8_t *__restrict__ near, float *__restrict__ X) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch < 2^31
+    if (k >= rows * g.n_p) return;
+    const int jr = j0 + k / g.n_p, q = k % g.n_p;
     const int j = row_base + jr;   // index into the sorted events
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
-    const double et = (double)se[j];   // E - e_c
+    const float et = se[j];   // E - e_c
     double uq, dq;
     pixel_frame(g, st, q, a, uq, dq);
-    const double gk = k_resp(g, u - uq);
-    double h = 0.0;
-    if (gk > 0.0) {
-        const double beta0 = 2.0 * g.c2 * (g.e0 - g.e_c);
-        h = gk * exp2((double)st.prim[(size_t)a * g.n_p + q] + beta0 * et);
-        // near field: the ends of q's band that the event reaches
+    const double reach = 3.0 * g.sig_u;
+    const bool is_near = fabs(u - uq) < reach;
+    float h = 0.0f;
+    if (is_near) {
+        const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
+        const float beta0 = (float)(2.0 * g.c2 * (g.e0 - g.e_c));
+        h = k_resp_f((float)(u - uq), inv2s2) *
+            __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
+        // near field: the ends the event reaches, all inside q's band
         const double *us = st.us_sorted + (size_t)a * g.n_p;
-        const double reach = 3.0 * g.sig_u;
         const int lo = band_lo[(size_t)a * g.n_p + q];
         const float2 *bq = band + (size_t)a * band_w * g.n_qpad + q;
-        for (int b = 0; b < band_w && lo + b < g.n_p; ++b) {
-            const double d = u - us[lo + b];
-            if (d <= -reach) break;
-            const double gs = k_resp(g, d);
-            if (gs <= 0.0) continue;
+        const int2 r = rr[j - row_base];
+        const int b0 = max(r.x - lo, 0), b1 = min(r.y - lo, band_w);
+        for (int b = b0; b < b1; ++b) {
             const float2 ab = bq[(size_t)b * g.n_qpad];
-            h += gs * exp2((double)ab.x + (double)ab.y * et);
+            h = fmaf(k_resp_f((float)(u - us[lo + b]), inv2s2), __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)), h);
         }
-        h *= (double)efac[j];
+        h *= efac[j];
     }
-    H[(size_t)jr * g.n_qpad + q] = (float)h;
+    H[(size_t)jr * g.n_qpad + q] = h;
+    near[k] = is_near ? 1 : 0;
     float x[8];
-    features(g, st, q, a, u, et + g.e_c, col[j], x);
-    float *xo = X + k * 8;
+    features(g, st, q, a, u, (double)et + g.e_c, col[j - row_base], x);
+    float *xo = X + (size_t)k * 8;
 #pragma unroll
     for (int i = 0; i < 8; ++i) xo[i] = x[i];
 }
 
 // Inference, step 3: add the network's scatter estimate to the far-field pairs.
-__global__ void k_surr_add(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
-                           int row_base, int j0, int rows, const float *__restrict__ y, float *__restrict__ H) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)rows * g.n_p) return;
-    const int jr = j0 + (int)(k / g.n_p), q = (int)(k % g.n_p);
-    const int j = row_base + jr;
-    const int a = ev_angle[j];
-    const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
-    double uq, dq;
-    pixel_frame(g, st, q, a, uq, dq);
-    if (k_resp(g, u - uq) > 0.0) return;   // near field: exact
-    const double s0 = 1.0 / (g.dx * g.sig_e);
-    const float s = (float)(s0 * fmax(exp((double)y[k]) - (double)kTargetFloor, 0.0));
-    H[(size_t)jr * g.n_qpad + q] += s;
+__global__ void k_surr_add(Geo g, int j0, int rows, const uint8_t *__restrict__ near, const float *__restrict__ y,
+                           float *__restrict__ H) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= rows * g.n_p || near[k]) return;
+    const int jr = j0 + k / g.n_p, q = k % g.n_p;
+    const float s0 = (float)(1.0 / (g.dx * g.sig_e));
+    H[(size_t)jr * g.n_qpad + q] += s0 * fmaxf(__expf(y[k]) - kTargetFloor, 0.0f);
 }
 
 // partial means with one pixel group: pmean[j] = sum_q f[real(j)][q] H[j][q]
@@ -257,7 +266,7 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, g, s, t.p_pix + g.n_p,
                        t.T, pixel, angle, u_bin, energy, n, X, target, scatter);
     return hipGetLastError();
@@ -267,26 +276,27 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
 // H[j][q] = primary(q; A_j) + S_net(q; A_j), and the partial means (one group).
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *col, float *X, float *y,
-                          int64_t pair_cap, hipStream_t st) {
+                          int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X,
+                          float *y, int64_t pair_cap, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     float4 *col4 = reinterpret_cast<float4 *>(col);
+    int2 *rr = reinterpret_cast<int2 *>(col4 + rows);   // the workspace holds 6 words per event
     hipError_t e;
-    hipLaunchKernelGGL(k_event_column, dim3((rows + 255) / 256), dim3(256), 0, st, g, s, ev_angle + row_base,
-                       su + row_base, rows, col4 + row_base);
+    hipLaunchKernelGGL(k_event_column, dim3((rows + 63) / 64), dim3(64), 0, st, g, s, ev_angle + row_base,
+                       su + row_base, rows, col4, rr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rows_per = (int)std::max<int64_t>(1, pair_cap / g.n_p);
     for (int j0 = 0; j0 < rows; j0 += rows_per) {
         const int nr = std::min(rows_per, rows - j0);
         const int64_t pairs = (int64_t)nr * g.n_p;
         hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, t.band,
-                           t.band_w, t.band_lo, ev_angle, su, se, efac, col4, row_base, j0, nr, H, X);
+                           t.band_w, t.band_lo, ev_angle, su, se, efac, col4, rr, row_base, j0, nr, H, near, X);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         net_set_stream(net, st);
         if ((e = net_forward(net, X, pairs, y)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
-                           row_base, j0, nr, y, H);
+        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, near,
+                           y, H);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_row_mean, dim3(rows), dim3(64), 0, st, g, rrange, n_real, rows, H, f, pmean);

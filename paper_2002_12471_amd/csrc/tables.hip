@@ -115,7 +115,8 @@ __device__ double detector_mass(const Geo &g, double up) {
 
 // Rank path ends by detector position per angle (ties by index).
 __global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__restrict__ cs,
-                       int *__restrict__ s_sorted, double *__restrict__ us_sorted, double *__restrict__ D_sorted) {
+                       const float *__restrict__ mu, int *__restrict__ s_sorted, double *__restrict__ us_sorted,
+                       float *__restrict__ mu_sorted, double *__restrict__ D_sorted) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     int a = blockIdx.y;
     if (p >= g.n_p) return;
@@ -131,6 +132,7 @@ __global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__res
     size_t o = (size_t)a * g.n_p + rank;
     s_sorted[o] = p;
     us_sorted[o] = u;
+    mu_sorted[o] = mu[pix];
     D_sorted[o] = detector_mass(g, u);
 }
 
@@ -281,6 +283,7 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
     CK(hipMalloc(&sens_a, sizeof(double) * g.n_angles * g.n_qpad), "alloc sens_a");
     CK(hipMalloc(&t.s_sorted, sizeof(int) * g.n_angles * g.n_p), "alloc ranks");
     CK(hipMalloc(&t.us_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc positions");
+    CK(hipMalloc(&t.mu_sorted, sizeof(float) * g.n_angles * g.n_p), "alloc positions");
     if (store_paths) CK(hipMalloc(&t.T, sizeof(float2) * nT), "alloc path table");
     CK(hipMalloc(&t.Ldet, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
     CK(hipMalloc(&t.Lback, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
@@ -288,7 +291,7 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
     CK(hipMalloc(&t.sens, sizeof(float) * g.n_subsets * g.n_qpad), "alloc sens");
     CK(hipMalloc(&t.sens_all, sizeof(float) * g.n_qpad), "alloc sens_all");
     bytes = (int64_t)((store_paths ? sizeof(float2) * nT : 0) + 3 * sizeof(float) * g.n_angles * g.n_p +
-                      sizeof(int) * g.n_angles * g.n_p +
+                      sizeof(int) * g.n_angles * g.n_p + sizeof(float) * g.n_angles * g.n_p +
                       sizeof(double) * g.n_angles * g.n_p + sizeof(float) * (g.n_subsets + 1) * g.n_qpad);
 
     int na_np = g.n_angles * g.n_p;
@@ -304,7 +307,7 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
         CK(hipGetLastError(), "scatter points");
     }
     hipLaunchKernelGGL(k_rank, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix,
-                       t.cs, t.s_sorted, t.us_sorted, D_sorted);
+                       t.cs, t.mu, t.s_sorted, t.us_sorted, t.mu_sorted, D_sorted);
     CK(hipGetLastError(), "rank");
     hipLaunchKernelGGL(k_path_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g,
                        t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a, t.prim);

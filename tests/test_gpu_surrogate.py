@@ -50,12 +50,13 @@ def test_network_forward_matches_reference(dev):
         L.lmosem_net_destroy(net)
 
 
-def test_network_gradient_matches_reference(dev):
+@pytest.mark.parametrize("count", [256, 2048])   # 2048: weight gradients split over the batch
+def test_network_gradient_matches_reference(dev, count):
     L = _lib()
     p = _params(6)
     rng = np.random.default_rng(2)
-    X = rng.normal(size=(256, 8)).astype(np.float32)
-    dy = rng.normal(size=256).astype(np.float32) / 256
+    X = rng.normal(size=(count, 8)).astype(np.float32)
+    dy = rng.normal(size=count).astype(np.float32) / count
     net = L.lmosem_net_create(p)
     try:
         g = L.lmosem_net_gradient(net, torch.as_tensor(X, device=dev), torch.as_tensor(dy, device=dev))
