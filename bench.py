@@ -106,6 +106,17 @@ def cpu_baseline(w, act, mu, ev, n_sample=1024, seed=11):
                       f"threads; model build {t_model:.1f} s not counted)"}
 
 
+# VALU issue rate of the chip (lane-slots/s): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz; packed FP32 is compiled out.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Fused network, VALU lane-slots per (event, pixel) pair: 384 GELUs of five
+# full-rate operations and two half-rate transcendentals (exp2, rcp), 192
+# packed bf16 conversions, and the output row (128 bf16 widenings + 128 FMAs).
+# The MFMA work (67,840 flops per pair at 2.5 PFLOP/s) needs a quarter of
+# that time, so the VALU bounds the kernel.
+MLP_SLOTS_PER_PAIR = 384 * (5 + 2 * 2) + 192 + 256
+
+
 def bench_surrogate(args, L, torch, np, synth):
     """Train the scatter surrogate (224 random maps, 32 held out) and compare
     it with the exact path on the tiny disk workload: event-mean error,
@@ -173,6 +184,24 @@ def bench_surrogate(args, L, torch, np, synth):
         torch.cuda.synchronize()
         rates[k] = J * args.steps / (e0.elapsed_time(e1) * 1e-3)
         L.lmosem_events_free(evs)
+    # dominant kernel: the fused network over one iteration's (event, pixel) pairs
+    n_pairs = J * int(ctxs["surrogate"].stats()["n_support"])
+    gx = torch.Generator(device=dev).manual_seed(5)
+    Xr = (torch.rand(n_pairs, 8, device=dev, generator=gx) - 0.5).contiguous()
+    yr = torch.empty(n_pairs, device=dev)
+    for _ in range(2):
+        L.lmosem_net_forward(net, Xr, yr)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        L.lmosem_net_forward(net, Xr, yr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_mlp = e0.elapsed_time(e1) * 1e-3 / reps
+    pairs_s = n_pairs / t_mlp
+    peak_pairs = VALU_SLOTS_PER_S / MLP_SLOTS_PER_PAIR
     table = {k: ctxs[k].stats()["table_bytes"] for k in ("exact", "surrogate")}
     for c in ctxs.values():
         c.close()
@@ -191,6 +220,9 @@ def bench_surrogate(args, L, torch, np, synth):
         "mean_rel_event_error": rel, "mean_rel_event_error_at_iter10_image": rel10,
         "image_rel_l2_vs_exact_recon_iter10": img_err,
         "table_bytes": table,
+        "roofline": {"bound": "alu", "kernel": "k_mlp_infer", "achieved": pairs_s / 1e9, "peak": peak_pairs / 1e9,
+                     "unit": "Gpair/s", "frac": pairs_s / peak_pairs, "traffic": None,
+                     "launch_us": t_mlp * 1e6, "pairs_per_launch": n_pairs},
         "train": {"samples": int(X.shape[0]), "epochs": args.surrogate_epochs, "loss_first": float(loss[0]),
                   "loss_last": float(loss[-1]), "heldout_mse": val, "sample_s": t_samples, "train_s": t_train},
     }
@@ -345,7 +377,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (Monte-Carlo list-mode events from analytic brain phantom)",
+        "data": "synthetic (Monte-Carlo list-mode events from the analytic %s phantom)" % (
+            "brain" if w.phantom == "brain" else "disk"),
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "events": J, "realisations": n_real, "subsets": g["n_subsets"],
                    "support_pixels": int((mu > 0).sum()),

@@ -90,7 +90,8 @@ typedef struct {
     int32_t n_subsets;        /* 1 .. n_angles */
     int32_t scatter_model;    /* 0: primary paths only; 1: primary + first-order scatter;
                                  2: primary + learned first-order scatter (needs a network,
-                                 lmosem_set_surrogate; no path table is stored) */
+                                 lmosem_set_surrogate; only the near-field band of the
+                                 path table is stored) */
     double acq_time;          /* T (> 0) */
 } lmosem_config;
 
@@ -245,23 +246,32 @@ lmosem_status lmosem_set_timing(lmosem_ctx *ctx, int32_t enable);
 lmosem_status lmosem_measure_alu_rates(void *hip_stream, double *out3);
 
 /* ---- learned scatter surrogate -------------------------------------
- * Not part of the paper: a network S_net(x) replaces the first-order scatter
- * part of each system row, S(q; a, u, E) = sum_{s != q} s_eff-weighted
- * K G terms (Sec. 2.2), one evaluation per (event, emission pixel), while
- * the primary term stays exact.  Network: 8 -> 128 -> 128 -> 128 -> 1, GELU
+ * Not part of the paper: a network S_net(x) stands in for the first-order
+ * scatter part of each system row, S(q; a, u, E) = sum_{s != q} s_eff-weighted
+ * K G terms (Sec. 2.2), one evaluation per (event, emission pixel), for the
+ * pairs whose event lies outside q's own position response
+ * (|u - u_q| >= 3 sigma_u).  Inside it (the near field) the scatter sum is
+ * exact, from a table of the path ends within 6 sigma_u of u_q, and the
+ * primary term is always exact.  Network: 8 -> 128 -> 128 -> 128 -> 1, GELU
  * (tanh form), bf16 weights and activations with FP32 accumulation on MFMA,
- * FP32 master weights, Adam.  Inputs x (8 floats per pair) and the target
- * y = ln(S / S0 + 1e-4), S0 = 1 / (pixel_cm * sigma_E), are produced by
- * lmosem_surrogate_samples.  Parameters are passed flat (34305 floats):
- * W1[8][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[128] b4,
- * W[in][out]. */
+ * FP32 master weights, Adam.  Inputs x (8 floats per pair: offset from q's
+ * detector position, energy, where the event's detector line enters and
+ * leaves the body relative to q's depth, that line's response-weighted
+ * attenuation, attenuation from q toward and away from the detector, mu at
+ * q) and the target y = ln(S / S0 + 1e-4), S0 = 1 / (pixel_cm * sigma_E), are
+ * produced by lmosem_surrogate_samples.  Parameters are passed flat (34305
+ * floats): W1[8][128] b1[128] W2[128][128] b2[128] W3[128][128] b3[128]
+ * W4[128] b4, W[in][out].  A context runs the network on its own stream: do
+ * not train a network while a context iterates with it. */
 
-/* New network from host parameters; its kernels run on hip_stream. */
+/* New network from host parameters; its kernels run on hip_stream (the
+ * weights are ready on every stream when this returns). */
 lmosem_status lmosem_net_create(const float *params_host, void *hip_stream, lmosem_net **out);
 void lmosem_net_destroy(lmosem_net *net);
 /* Current FP32 master parameters into params_host[34305] (synchronises). */
 lmosem_status lmosem_net_get_params(lmosem_net *net, float *params_host);
-/* y_dev[n] = network(X_dev[n][8]). */
+/* y_dev[n] = network(X_dev[n][8]), on the network's stream; one fused kernel
+ * (all four layers, weights in LDS). */
 lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n, float *y_dev);
 /* Gradient of sum_i dy_dev[i] y_i over all parameters into grad_host[34305];
  * n a positive multiple of 16 (synchronises). */
@@ -276,7 +286,9 @@ lmosem_status lmosem_net_train(lmosem_net *net, const float *X_dev, const float 
 /* Training samples on a scatter_model-1 context: for each (support pixel,
  * angle, u_bin, energy) the network inputs X_dev[n][8], the target
  * target_dev[n] and (nullable) the exact scatter sum scatter_dev[n], from the
- * exact path table.  Errors: ENOTSUP without a path table, ERANGE. */
+ * exact path table (any u; the network is meant for the far field).
+ * Errors: ENOTSUP without a path table, ERANGE for a pixel off the support
+ * or an invalid angle, position or energy. */
 lmosem_status lmosem_surrogate_samples(lmosem_ctx *ctx, const int32_t *pixel, const int32_t *angle,
                                        const float *u_bin, const float *energy, int64_t n, float *X_dev,
                                        float *target_dev, float *scatter_dev);

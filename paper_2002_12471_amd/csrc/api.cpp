@@ -632,7 +632,7 @@ lmosem_status lmosem_net_get_params(lmosem_net *net, float *params_host) {
 
 lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n, float *y_dev) {
     if (!net || n < 0 || (n > 0 && (!X_dev || !y_dev))) return LMOSEM_EINVAL;
-    return net_forward(net->n, X_dev, n, y_dev) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+    return net_forward(net->n, X_dev, n, y_dev, net_stream(net->n)) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
 }
 
 lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const float *dy_dev, int32_t n,

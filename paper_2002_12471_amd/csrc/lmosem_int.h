@@ -118,9 +118,9 @@ struct Net;
 extern const int kNetParams;
 hipError_t net_create(const float *params_host, hipStream_t st, Net **out);
 void net_destroy(Net *n);
-void net_set_stream(Net *n, hipStream_t st);
+hipStream_t net_stream(const Net *n);   // the stream the network was created on
 hipError_t net_get_params(Net *n, float *host);
-hipError_t net_forward(Net *n, const float *X, int64_t count, float *y);
+hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStream_t st);
 hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host);
 hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
                      float lr_decay, double *loss_host);

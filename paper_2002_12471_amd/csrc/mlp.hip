@@ -540,6 +540,8 @@ hipError_t net_create(const float *params_host, hipStream_t st, Net **out) {
     hipLaunchKernelGGL(k_pack, dim3((kHid * kHid + 255) / 256), dim3(256), 0, st, n->p, n->nb);
     hipLaunchKernelGGL(k_pack_fused, dim3((2 * kFW2 + 255) / 256), dim3(256), 0, st, n->p, n->fw, n->fb);
     if ((e = hipGetLastError()) != hipSuccess) return bail(e);
+    // contexts run the network on their own streams: the weights are ready on return
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
     *out = n;
     return hipSuccess;
 }
@@ -553,7 +555,7 @@ void net_destroy(Net *n) {
     delete n;
 }
 
-void net_set_stream(Net *n, hipStream_t st) { n->st = st; }
+hipStream_t net_stream(const Net *n) { return n->st; }
 
 hipError_t net_get_params(Net *n, float *host) {
     hipError_t e = hipMemcpyAsync(host, n->p, kNParams * 4, hipMemcpyDeviceToHost, n->st);
@@ -602,11 +604,11 @@ static hipError_t backward_batch(Net &n, const float *dy, int nb) {
     return hipGetLastError();
 }
 
-hipError_t net_forward(Net *n, const float *X, int64_t count, float *y) {
+hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int64_t tiles = (count + kFusedTile - 1) / kFusedTile;
     const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2 * 256);   // two workgroups per CU
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, n->st, n->fw, n->fb, X, count, y);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, st, n->fw, n->fb, X, count, y);
     return hipGetLastError();
 }
 

@@ -293,8 +293,7 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
         hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, t.band,
                            t.band_w, t.band_lo, ev_angle, su, se, efac, col4, rr, row_base, j0, nr, H, near, X);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        net_set_stream(net, st);
-        if ((e = net_forward(net, X, pairs, y)) != hipSuccess) return e;
+        if ((e = net_forward(net, X, pairs, y, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, near,
                            y, H);
         if ((e = hipGetLastError()) != hipSuccess) return e;
