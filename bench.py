@@ -60,8 +60,8 @@ def mix_peak_terms_per_s():
 
 def profiled_traffic(event_tile, workload):
     """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None if the kernel source or tile size changed
-    since the counters were taken."""
+    WRITE_SIZE summary for this event tile, or None if the kernel source
+    changed since the counters were taken or the tile was not profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_forward_brain64.md")
     src = os.path.join(ROOT, "paper_2002_12471_amd", "csrc", "osem.hip")
@@ -72,10 +72,10 @@ def profiled_traffic(event_tile, workload):
                 k, v = line.split(":", 1)
                 fields[k.split(" (")[0].strip()] = v.strip()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if (workload != "brain64" or fields.get("source_sha256") != sha
-                or int(fields.get("event_tile", -1)) != event_tile):
+        key = f"traffic_bytes_per_launch_ev{event_tile}"
+        if workload != "brain64" or fields.get("source_sha256") != sha or key not in fields:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (OSError, KeyError, ValueError):
         return None
 
