@@ -118,16 +118,20 @@ MLP_SLOTS_PER_PAIR = 384 * (5 + 2 * 2) + 192 + 256
 
 
 def bench_surrogate(args, L, torch, np, synth):
-    """Train the scatter surrogate (224 random maps, 32 held out) and compare
-    it with the exact path on the tiny disk workload: event-mean error,
-    image error after 10 iterations, and events/s of one iteration."""
+    """Train the scatter surrogate on random maps (the last 32 held out) and
+    compare it with the exact path: on the tiny disk (maps on the 16x16 grid)
+    or, with --workload surrogate128, on the 128x128 brain (maps on that grid):
+    event-mean error, image (and striatal uptake) error after 10 iterations,
+    and events/s of whole iterations."""
     from paper_2002_12471_amd import surrogate as S
+    large = args.workload == "surrogate128"
     dev = torch.device("cuda:0")
-    wm = synth.workload("surrogate_maps")
+    wm = synth.workload("surrogate_maps_128" if large else "surrogate_maps")
     gm = wm.geom.as_dict()
     rng = np.random.default_rng(synth.seed_for(wm))
     n_maps, per_map = wm.extra["n_maps"], wm.extra["n_samples"] // wm.extra["n_maps"]
-    maps = [synth.random_ellipse_map(wm.geom, rng) for _ in range(n_maps)]
+    maps = [synth.random_ellipse_map(wm.geom, rng, wm.extra.get("shell_prob", 0.0), wm.extra.get("body", (0.4, 0.9)))
+            for _ in range(n_maps)]
     draws = [synth.surrogate_sample_inputs(wm.geom, m, per_map, rng) for m in maps]
     log(f"surrogate samples: {n_maps} maps x {per_map}")
     torch.cuda.synchronize()
@@ -136,7 +140,7 @@ def bench_surrogate(args, L, torch, np, synth):
     Xv, tv = S.make_samples(gm, maps[-32:], draws[-32:], dev)
     torch.cuda.synchronize()
     t_samples = time.time() - t0
-    log("training")
+    log(f"training ({t_samples:.1f} s of samples)")
     t0 = time.time()
     net, loss = S.train(synth.mlp_init_params(synth.seed_for(wm, 1)), X, t, rng.permutation(X.shape[0]),
                         batch=4096, epochs=args.surrogate_epochs, lr=2e-3, lr_decay=0.93)
@@ -144,48 +148,71 @@ def bench_surrogate(args, L, torch, np, synth):
     t_train = time.time() - t0
     val = S.mse(net, Xv, tv)
 
-    w = synth.workload("tiny")
+    w = synth.workload("brain128" if large else "tiny")
     g = w.geom.as_dict()
     act, mu = synth.phantom(w)
-    ev = L.events_to_device(synth.workload_events(w), dev)
+    ev_np = synth.workload_events(w)
+    ev = L.events_to_device(ev_np, dev)
+    J = int(ev["angle"].numel())
+    if large:   # per-event errors on a seeded 64k subsample
+        idx = np.sort(np.random.default_rng(synth.seed_for(w, 777)).choice(J, 65536, replace=False))
+        ev_eval = L.events_to_device({k: ev_np[k][idx] for k in ("angle", "u_bin", "energy")}, dev)
+    else:
+        ev_eval = ev
     mu_d = torch.as_tensor(mu, device=dev)
     ctxs = {"exact": L.Context(g, mu_d), "primary": L.Context(dict(g, scatter_model=0), mu_d),
             "surrogate": L.Context(dict(g, scatter_model=2), mu_d)}
     L.lmosem_set_surrogate(ctxs["surrogate"].handle, net)
     img = torch.as_tensor(act, device=dev)
-    means = {k: c.forward(ev, img).double() for k, c in ctxs.items()}
+    log("event means and reconstructions")
+    means = {k: c.forward(ev_eval, img).double() for k, c in ctxs.items()}
     recon = {k: c.reconstruct(ev, 10).double() for k, c in ctxs.items()}
-    rel = {k: float(((means[k] - means["exact"]).abs() / means["exact"]).mean()) for k in ("surrogate", "primary")}
+    def mean_rel(a, b):   # over events with a positive exact mean (the rest are skipped by every path)
+        ok = b > 0
+        return float(((a[ok] - b[ok]).abs() / b[ok]).mean())
+    rel = {k: mean_rel(means[k], means["exact"]) for k in ("surrogate", "primary")}
     ref = recon["exact"]
     img_err = {k: float(((recon[k] - ref) ** 2).sum().sqrt() / (ref ** 2).sum().sqrt())
                for k in ("surrogate", "primary")}
     rel10 = {}
     for k in ("surrogate", "primary"):
-        m_e = ctxs["exact"].forward(ev, recon["exact"].float().contiguous()).double()
-        m_k = ctxs[k].forward(ev, recon["exact"].float().contiguous()).double()
-        rel10[k] = float(((m_k - m_e).abs() / m_e).mean())
-    # throughput: one full iteration per step, inputs resident
+        m_e = ctxs["exact"].forward(ev_eval, recon["exact"].float().contiguous()).double()
+        m_k = ctxs[k].forward(ev_eval, recon["exact"].float().contiguous()).double()
+        rel10[k] = mean_rel(m_k, m_e)
+    uptake = None
+    if large:   # striatal uptake after 10 iterations: region mean over the brain background mean
+        caud, put = synth.striatal_masks(w.geom)
+        bg = (act > 0) & ~caud & ~put
+        bg_t = torch.as_tensor(bg, device=dev)
+        uptake = {}
+        for name, m in (("caudate", caud), ("putamen", put)):
+            mt = torch.as_tensor(m & (act > 0), device=dev)
+            uptake[name] = {"truth": float(act[m & (act > 0)].mean() / act[bg].mean()),
+                            **{k: float(recon[k][mt].mean() / recon[k][bg_t].mean())
+                               for k in ("exact", "surrogate", "primary")}}
+    # throughput: whole iterations, inputs resident
     rates = {}
-    J = int(ev["angle"].numel())
+    steps, warm = (min(args.steps, 3), min(args.warmup, 1)) if large else (args.steps, args.warmup)
     stream = torch.cuda.current_stream(dev)
     for k in ("exact", "surrogate"):
+        log(f"timing {k}")
         c = ctxs[k]
         evs = L.lmosem_events_load(c.handle, ev)
         L.lmosem_autotune(c.handle, evs)
         x = torch.as_tensor((mu > 0).astype(np.float32), device=dev).contiguous()
-        for _ in range(args.warmup):
+        for _ in range(warm):
             L.lmosem_iterate(c.handle, evs, 1, x)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             L.lmosem_iterate(c.handle, evs, 1, x)
         e1.record(stream)
         torch.cuda.synchronize()
-        rates[k] = J * args.steps / (e0.elapsed_time(e1) * 1e-3)
+        rates[k] = J * steps / (e0.elapsed_time(e1) * 1e-3)
         L.lmosem_events_free(evs)
-    # dominant kernel: the fused network over one iteration's (event, pixel) pairs
-    n_pairs = J * int(ctxs["surrogate"].stats()["n_support"])
+    # dominant kernel: the fused network over one batch of (event, pixel) pairs
+    n_pairs = min(int(ev_eval["angle"].numel()) * int(ctxs["surrogate"].stats()["n_support"]), 1 << 22)
     gx = torch.Generator(device=dev).manual_seed(5)
     Xr = (torch.rand(n_pairs, 8, device=dev, generator=gx) - 0.5).contiguous()
     yr = torch.empty(n_pairs, device=dev)
@@ -203,22 +230,27 @@ def bench_surrogate(args, L, torch, np, synth):
     pairs_s = n_pairs / t_mlp
     peak_pairs = VALU_SLOTS_PER_S / MLP_SLOTS_PER_PAIR
     table = {k: ctxs[k].stats()["table_bytes"] for k in ("exact", "surrogate")}
+    n_sup = int(ctxs["exact"].stats()["n_support"])
     for c in ctxs.values():
         c.close()
     L.lmosem_net_destroy(net)
+    grid = (f"{wm.geom.nx}x{wm.geom.ny} px of {wm.geom.pixel_cm} cm")
+    target = ("the 128x128 brain (2M events, 16 subsets; event errors on a seeded 64k subsample)" if large
+              else "the tiny disk (5000 events, 1 subset)")
     out = {
         "metric": METRIC, "value": rates["surrogate"], "unit": "events/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": J / rates["surrogate"] * 1e3,
+        "steps": steps, "warmup": warm, "ms_per_step": J / rates["surrogate"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32",
         "data": "synthetic (Monte-Carlo list-mode events; random elliptical training maps)",
-        "config": {"workload": "surrogate: MLP 8-128-128-128-1 GELU, bf16 MFMA with FP32 accumulation, "
-                               f"trained on {X.shape[0]} samples from {n_maps - 32} random elliptical maps "
-                               "(mu 0.1-0.3/cm, 16x16 px of 0.8 cm), used in LM-OSEM on the tiny disk "
-                               "(5000 events, 1 subset)", "events": J},
+        "config": {"workload": f"{args.workload}: MLP 8-128-128-128-1 GELU, bf16 MFMA with FP32 accumulation, "
+                               f"trained on {X.shape[0]} far-field samples from {n_maps - 32} random elliptical "
+                               f"maps (mu 0.1-0.3/cm, {grid}), near field exact, used in LM-OSEM on {target}",
+                   "events": J, "support_pixels": n_sup},
         "exact_value": rates["exact"],
         "surrogate_vs_exact_speed": rates["surrogate"] / rates["exact"],
         "mean_rel_event_error": rel, "mean_rel_event_error_at_iter10_image": rel10,
         "image_rel_l2_vs_exact_recon_iter10": img_err,
+        "striatal_uptake_ratio_iter10": uptake,
         "table_bytes": table,
         "roofline": {"bound": "alu", "kernel": "k_mlp_infer", "achieved": pairs_s / 1e9, "peak": peak_pairs / 1e9,
                      "unit": "Gpair/s", "frac": pairs_s / peak_pairs, "traffic": None,
@@ -237,7 +269,7 @@ def main():
     ap.add_argument("--event-tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="brain64",
-                    choices=["brain64", "tiny", "batch_tiny", "brain128", "surrogate"])
+                    choices=["brain64", "tiny", "batch_tiny", "brain128", "surrogate", "surrogate128"])
     ap.add_argument("--surrogate-epochs", type=int, default=40)
     ap.add_argument("--realisations", type=int, default=0,
                     help="realisations for the batched workloads (default: 64 for batch_tiny, 2 for brain128)")
@@ -259,7 +291,7 @@ def main():
         __graft_entry__.build()
     from paper_2002_12471_amd import lmosem as L
 
-    if args.workload == "surrogate":
+    if args.workload in ("surrogate", "surrogate128"):
         bench_surrogate(args, L, torch, np, synth)
         return
     dev = torch.device("cuda:0")

@@ -283,12 +283,14 @@ lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const flo
  * receives each epoch's mean loss. */
 lmosem_status lmosem_net_train(lmosem_net *net, const float *X_dev, const float *t_dev, int64_t n, int32_t batch,
                                int32_t epochs, float lr, float lr_decay, double *loss_host);
-/* Training samples on a scatter_model-1 context: for each (support pixel,
- * angle, u_bin, energy) the network inputs X_dev[n][8], the target
- * target_dev[n] and (nullable) the exact scatter sum scatter_dev[n], from the
- * exact path table (any u; the network is meant for the far field).
- * Errors: ENOTSUP without a path table, ERANGE for a pixel off the support
- * or an invalid angle, position or energy. */
+/* Training samples on a scatter_model-1 or -2 context: for each (support
+ * pixel, angle, u_bin, energy) the network inputs X_dev[n][8], the target
+ * target_dev[n] and (nullable) the exact first-order scatter sum
+ * scatter_dev[n] (Sec. 2.2), every path weight evaluated in FP64 from the
+ * context's line integrals and scatter-point factors (no full path table is
+ * needed; any u is accepted, the network is meant for the far field).
+ * Errors: ENOTSUP for scatter_model 0, ERANGE for a pixel off the support or
+ * an invalid angle, position or energy. */
 lmosem_status lmosem_surrogate_samples(lmosem_ctx *ctx, const int32_t *pixel, const int32_t *angle,
                                        const float *u_bin, const float *energy, int64_t n, float *X_dev,
                                        float *target_dev, float *scatter_dev);

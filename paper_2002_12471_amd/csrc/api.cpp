@@ -459,7 +459,7 @@ void lmosem_destroy(lmosem_ctx *c) {
     if (c->gst) hipStreamDestroy(c->gst);
     hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted); hipFree(c->t.mu_sorted);
     hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->t.Ldet); hipFree(c->t.Lback);
-    hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->bad_dev); hipFree(c->skipped_dev);
+    hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->t.Ld); hipFree(c->t.Bt); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;
 }
 
@@ -653,7 +653,8 @@ lmosem_status lmosem_surrogate_samples(lmosem_ctx *c, const int32_t *pixel, cons
                                        const float *u_bin, const float *energy, int64_t n, float *X_dev,
                                        float *target_dev, float *scatter_dev) {
     GUARD(c);
-    if (!c->t.T) return set_err(c, LMOSEM_ENOTSUP, "training samples need the exact path table (scatter_model 1)");
+    if (!c->t.Bt)
+        return set_err(c, LMOSEM_ENOTSUP, "training samples need the first-order scatter model (scatter_model 1 or 2)");
     if (n < 0 || (n > 0 && (!pixel || !angle || !u_bin || !energy || !X_dev || !target_dev)))
         return set_err(c, LMOSEM_EINVAL, "bad sample arrays");
     // the samples' angles, positions and energies follow the event rules;

@@ -65,6 +65,10 @@ struct Tables {
     float *Ldet = nullptr;       // [n_angles][n_p] attenuation from the pixel centre to the detector
     float *Lback = nullptr;      // [n_angles][n_p] attenuation from the pixel centre away from it
     float *prim = nullptr;       // [n_angles][n_p] alpha of each pixel's primary path
+    // scatter contexts: per-angle line integrals and scatter-point factors,
+    // kept for exact path weights evaluated on the fly (training targets)
+    double *Ld = nullptr;        // [n_angles][n_p] L_a(p)
+    double *Bt = nullptr;        // [n_p][n_p] B(q, s) at [s][q]
     // learned-scatter contexts: exact near-field paths of each emission pixel
     float2 *band = nullptr;      // [n_angles][band_w][n_qpad] (alpha, beta), rank band_lo + k
     int *band_lo = nullptr;      // [n_angles][n_p] first rank of each pixel's band

@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "lmosem_int.h"
+#include "paths.h"
 
 namespace lmo {
 
@@ -143,31 +144,35 @@ __device__ inline void features(const Geo &g, const SurrTables &st, int q, int a
     x[7] = 10.0f * st.mu[st.p_pix[q]];
 }
 
-// Training samples: features and the exact target from the path table.
+// Training samples: features and the exact target, with every path weight
+// evaluated from the per-angle line integrals and scatter-point factors (the
+// function the table build uses), in FP64.
 __global__ void k_surr_samples(Geo g, SurrTables st, const int *__restrict__ q_of_pix,
-                               const float2 *__restrict__ T, const int32_t *__restrict__ pixel,
-                               const int32_t *__restrict__ angle, const float *__restrict__ u_bin,
-                               const float *__restrict__ energy, int64_t n, float *__restrict__ X,
-                               float *__restrict__ target, float *__restrict__ scatter) {
+                               const double *__restrict__ Ld, const double *__restrict__ Bt,
+                               const int32_t *__restrict__ pixel, const int32_t *__restrict__ angle,
+                               const float *__restrict__ u_bin, const float *__restrict__ energy, int64_t n,
+                               float *__restrict__ X, float *__restrict__ target, float *__restrict__ scatter) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int q = q_of_pix[pixel[k]];
     const int a = angle[k];
     const double u = ((double)u_bin[k] - 0.5 * g.n_bins) * g.bin_cm;
     const double e = (double)energy[k];
-    const double ec = e - g.e_c;
-    const double efac = exp2(-g.c2 * ec * ec) / g.zk;
+    const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
     const double *us = st.us_sorted + (size_t)a * g.n_p;
     const double reach = 3.0 * g.sig_u;
+    const double gnorm = 1.0 / (sqrt(2.0 * M_PI) * g.sig_e * g.zk);   // G and K normalisers
     int lo = 0, hi = g.n_p;   // first rank with us > u - reach
     while (lo < hi) { const int m = (lo + hi) >> 1; if (us[m] > u - reach) hi = m; else lo = m + 1; }
     double s = 0.0;
     for (int r = lo; r < g.n_p && us[r] < u + reach; ++r) {
-        if (st.s_sorted[(size_t)a * g.n_p + r] == q) continue;   // the primary path
+        const int sp = st.s_sorted[(size_t)a * g.n_p + r];
+        if (sp == q) continue;   // the primary path
         const double gk = k_resp(g, u - us[r]);
         if (gk <= 0.0) continue;
-        const float2 ab = T[((size_t)a * g.n_rpad + r) * g.n_qpad + q];
-        s += gk * efac * exp2((double)ab.y * ec + (double)ab.x);
+        const PathW pw = path_weight(g, st.p_pix, Ld, Bt, nx, ny, a, q, sp);
+        const double de = e - pw.ep;
+        s += gk * pw.w * exp(-de * de / (2.0 * g.sig_e * g.sig_e)) * gnorm;
     }
     float x[8];
     features(g, st, q, a, u, e, column(g, st, a, u), x);
@@ -268,7 +273,7 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
     if (n <= 0) return hipSuccess;
     SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, g, s, t.p_pix + g.n_p,
-                       t.T, pixel, angle, u_bin, energy, n, X, target, scatter);
+                       t.Ld, t.Bt, pixel, angle, u_bin, energy, n, X, target, scatter);
     return hipGetLastError();
 }
 

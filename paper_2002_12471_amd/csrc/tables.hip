@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "lmosem_int.h"
+#include "paths.h"
 
 namespace lmo {
 
@@ -50,14 +51,6 @@ __device__ double traverse(const float *__restrict__ mu, int nx, int ny, double 
         if (i < 0 || i >= nx || j < 0 || j >= ny) break;
     }
     return sum;
-}
-
-// Klein-Nishina total cross-section in units of r_e^2.
-__device__ __host__ inline double kn_total(double e) {
-    double k = e / kMeC2;
-    double l = log1p(2.0 * k);
-    double k1 = 1.0 + k, k2 = 1.0 + 2.0 * k;
-    return 2.0 * M_PI * (k1 / (k * k) * (2.0 * k1 / k2 - l / k) + l / (2.0 * k) - (1.0 + 3.0 * k) / (k2 * k2));
 }
 
 // L_a(p): attenuation from the centre of support pixel p to the detector.
@@ -134,27 +127,6 @@ __global__ void k_rank(Geo g, const int *__restrict__ p_pix, const double *__res
     us_sorted[o] = u;
     mu_sorted[o] = mu[pix];
     D_sorted[o] = detector_mass(g, u);
-}
-
-// Weight w and end energy E' of the path from emission pixel q through path
-// end s at angle a (s == q: the primary path).
-struct PathW {
-    double w, ep;
-};
-
-__device__ inline PathW path_weight(const Geo &g, const int *__restrict__ p_pix, const double *__restrict__ L,
-                                    const double *__restrict__ Bt, double nx, double ny, int a, int q, int s) {
-    if (s == q) return {exp(-L[(size_t)a * g.n_p + q]), g.e0};
-    if (!g.scatter) return {0.0, g.e0};
-    const int pq = p_pix[q], ps = p_pix[s];
-    const int di = ps % g.nx - pq % g.nx, dj = ps / g.nx - pq / g.nx;
-    const double c = (di * nx + dj * ny) / sqrt((double)(di * di + dj * dj));
-    const double t = 1.0 + g.kappa * (1.0 - c);
-    const double P = 1.0 / t;
-    const double ep = g.e0 * P;
-    const double psi = P * P * (P + t - 1.0 + c * c);
-    const double rho = kn_total(ep) / g.sigma_kn_e0;
-    return {Bt[(size_t)s * g.n_p + q] * psi / g.psi_bar * exp(-rho * L[(size_t)a * g.n_p + s]), ep};
 }
 
 // (alpha, beta) code of a path weight; zero weight never contributes
@@ -333,6 +305,12 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
                        t.sens, t.sens_all);
     CK(hipGetLastError(), "sensitivity");
     CK(hipStreamSynchronize(st), "table build");
+    if (g.scatter) {   // kept for on-the-fly path weights
+        t.Ld = L;
+        t.Bt = Bt;
+        bytes += (int64_t)(sizeof(double) * ((size_t)g.n_angles * g.n_p + (size_t)g.n_p * g.n_p));
+        L = Bt = nullptr;
+    }
     hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
 #undef CK
     return hipSuccess;

@@ -1,8 +1,10 @@
 """Training driver of the learned scatter surrogate (orchestration only).
 
-For each attenuation map the caller supplies, a scatter_model-1 context
-builds the exact path table and lmosem_surrogate_samples turns the caller's
-(pixel, angle, u_bin, energy) draws into network inputs and exact targets;
+For each attenuation map the caller supplies, a learned-scatter context
+(scatter_model 2: line integrals, scatter-point factors and the near-field
+band, no full path table) is built and lmosem_surrogate_samples turns the
+caller's (pixel, angle, u_bin, energy) draws into network inputs and exact
+targets;
 the samples of all maps are shuffled with the caller's permutation and the
 network is trained by the library's own forward, backward and Adam kernels.
 """
@@ -18,7 +20,7 @@ def make_samples(geom: dict, maps, draws, device) -> tuple:
     """Inputs and targets for every (map, draws) pair, concatenated on the GPU."""
     Xs, ts = [], []
     for mu, s in zip(maps, draws):
-        ctx = L.Context(dict(geom, scatter_model=1), torch.as_tensor(mu, device=device))
+        ctx = L.Context(dict(geom, scatter_model=2), torch.as_tensor(mu, device=device))
         try:
             X, t = L.lmosem_surrogate_samples(ctx.handle, *[torch.as_tensor(s[k], device=device)
                                                             for k in ("pixel", "angle", "u_bin", "energy")])

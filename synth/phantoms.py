@@ -108,28 +108,38 @@ def striatal_masks(g: Geometry):
     return caud, put
 
 
-def random_ellipse_map(g: Geometry, rng: np.random.Generator):
+def random_ellipse_map(g: Geometry, rng: np.random.Generator, shell_prob: float = 0.0,
+                       body=(0.4, 0.9)):
     """Random elliptical attenuation map for surrogate training: a body
-    ellipse (semi-axes 0.4-0.9 of the half field of view) plus 0-2 inserts,
-    each with its own mu in [0.1, 0.3]/cm."""
+    ellipse (semi-axes a fraction `body` of the half field of view) plus 0-2
+    inserts, each with its own mu in [0.1, 0.3]/cm.  With probability
+    shell_prob the body gets a skull-like shell 0.4-1.2 cm thick with mu in
+    [0.2, 0.3]/cm (no random numbers are drawn for it when shell_prob is 0)."""
     X, Y = pixel_centres(g.nx, g.ny, g.pixel_cm)
     half = 0.5 * g.nx * g.pixel_cm
     mu = np.zeros_like(X)
-    body_a = rng.uniform(0.4, 0.9, size=2) * half
+    body_a = rng.uniform(body[0], body[1], size=2) * half
     c = rng.uniform(-0.2, 0.2, size=2) * half
-    body = _ellipse(X, Y, c[0], c[1], body_a[0], body_a[1], rng.uniform(0, 180))
-    mu[body] = rng.uniform(0.1, 0.3)
+    rot = rng.uniform(0, 180)
+    body_m = _ellipse(X, Y, c[0], c[1], body_a[0], body_a[1], rot)
+    mu[body_m] = rng.uniform(0.1, 0.3)
+    inside = body_m
+    if shell_prob > 0 and rng.uniform() < shell_prob:
+        t = rng.uniform(0.4, 1.2)
+        inside = _ellipse(X, Y, c[0], c[1], body_a[0] - t, body_a[1] - t, rot)
+        mu[body_m & ~inside] = rng.uniform(0.2, 0.3)
     for _ in range(rng.integers(0, 3)):
         ia = rng.uniform(0.1, 0.3, size=2) * half
         ic = c + rng.uniform(-0.3, 0.3, size=2) * half
-        ins = _ellipse(X, Y, ic[0], ic[1], ia[0], ia[1], rng.uniform(0, 180)) & body
+        ins = _ellipse(X, Y, ic[0], ic[1], ia[0], ia[1], rng.uniform(0, 180)) & inside
         mu[ins] = rng.uniform(0.1, 0.3)
     return mu.astype(np.float32)
 
 
 def workload(name: str) -> Workload:
-    """The five workloads: tiny disk, 64x64 brain, batched tiny realisations,
-    surrogate training maps, 128x128 brain."""
+    """The workloads: tiny disk, 64x64 brain, batched tiny realisations,
+    surrogate training maps (tiny grid), 128x128 brain, surrogate training
+    maps on the 128x128 grid."""
     if name == "tiny":
         g = Geometry(16, 16, 0.8, 16, 0.8, 16, win_lo_kev=100.0, win_hi_kev=175.0,
                      n_subsets=1)
@@ -149,10 +159,16 @@ def workload(name: str) -> Workload:
         g = Geometry(128, 128, 0.2, 256, 0.1, 120, win_lo_kev=90.0, win_hi_kev=175.0,
                      n_subsets=16)
         return Workload(name, g, 2_000_000, 10, "brain", n_real=16)
+    if name == "surrogate_maps_128":
+        g = Geometry(128, 128, 0.2, 256, 0.1, 120, win_lo_kev=90.0, win_hi_kev=175.0,
+                     n_subsets=16)
+        return Workload(name, g, 0, 10, "random_maps", extra={"n_maps": 256, "n_samples": 4_000_000,
+                                                              "shell_prob": 0.5, "body": (0.45, 0.8)})
     raise KeyError(name)
 
 
-WORKLOAD_INDEX = {"tiny": 1, "brain64": 2, "batch_tiny": 3, "surrogate_maps": 4, "brain128": 5}
+WORKLOAD_INDEX = {"tiny": 1, "brain64": 2, "batch_tiny": 3, "surrogate_maps": 4, "brain128": 5,
+                  "surrogate_maps_128": 6}
 
 
 def phantom(w: Workload):

@@ -114,6 +114,15 @@ def test_training_samples_match_oracle(dev):
         np.testing.assert_allclose(X[k], O.surrogate_features(m1, pix, a, u, e), rtol=1e-5, atol=1e-6)
         assert t[k] == pytest.approx(O.surrogate_target(ref, g), abs=2e-4)
     ctx.close()
+    # a learned-scatter context (no full path table) gives the same samples
+    ctx2 = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev))
+    X2, t2, S2 = L.lmosem_surrogate_samples(ctx2.handle, *[torch.as_tensor(s[k], device=dev)
+                                                          for k in ("pixel", "angle", "u_bin", "energy")],
+                                            want_scatter=True)
+    ctx2.close()
+    np.testing.assert_array_equal(X2.cpu().numpy(), X)
+    np.testing.assert_array_equal(t2.cpu().numpy(), t)
+    np.testing.assert_array_equal(S2.cpu().numpy(), S)
 
 
 def test_near_field_is_exact(dev):
