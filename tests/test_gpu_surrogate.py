@@ -50,6 +50,28 @@ def test_network_forward_matches_reference(dev):
         L.lmosem_net_destroy(net)
 
 
+def test_network_forward_every_workgroup_loops(dev):
+    """Enough rows that every workgroup of the fused kernel's grid (two per CU)
+    takes several 128-row steps, with a ragged tail; sampled rows (the tail
+    included) against the FP64 reference."""
+    L = _lib()
+    p = _params(8)
+    n = 512 * 128 * 3 + 37
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(n, 8)).astype(np.float32)
+    net = L.lmosem_net_create(p)
+    try:
+        y = torch.empty(n, device=dev)
+        L.lmosem_net_forward(net, torch.as_tensor(X, device=dev), y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+    finally:
+        L.lmosem_net_destroy(net)
+    idx = np.concatenate([np.sort(rng.choice(n - 37, 4000, replace=False)), np.arange(n - 37, n)])
+    ref, _ = M.forward(p, X[idx], bf16_round=True)
+    assert np.max(np.abs(got[idx] - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("count", [256, 2048])   # 2048: weight gradients split over the batch
 def test_network_gradient_matches_reference(dev, count):
     L = _lib()
