@@ -232,6 +232,18 @@ lmosem_status lmosem_autotune(lmosem_ctx *ctx, lmosem_evset *set, int32_t *event
  * on entry and before it on exit. */
 lmosem_status lmosem_set_graphs(lmosem_ctx *ctx, int32_t enable);
 
+/* Keep the system rows of a prepared set across iterations (enable = 1) or
+ * stop (0).  The rows h_j(q) do not depend on the estimate (Eq. 8 divides
+ * them only by the event means), so after one iteration has computed and
+ * stored all of them (n events x padded support x 4 bytes, allocated here,
+ * owned by the set, zero-filled), every later sub-iteration reads them twice
+ * from HBM (the event means, then the backprojection of Eq. 7) instead of
+ * recomputing every path term.  Results equal the recomputing path up to
+ * FP32 summation order.  Autotuning the set, or enabling again after
+ * disabling, recomputes the rows at the next iteration.  Errors: ENOMEM (the
+ * set stays usable without the cache), EINVAL. */
+lmosem_status lmosem_cache_rows(lmosem_ctx *ctx, lmosem_evset *set, int32_t enable);
+
 /* Counters of this context (synchronises the context's stream). */
 lmosem_status lmosem_get_stats(const lmosem_ctx *ctx, lmosem_stats *out);
 

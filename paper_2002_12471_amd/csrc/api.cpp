@@ -52,7 +52,10 @@ struct lmosem_evset {
     float *pb = nullptr;      // [max_chunks][n_qpad]
     float *f = nullptr;       // [n_real][n_qpad]
     double *ll = nullptr;     // [n_real]
-    hipGraphExec_t exec[2] = {nullptr, nullptr};   // one iteration without / with the log-likelihood
+    // one iteration captured as a graph: [with log-likelihood + 2 * from cached rows]
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *Hc = nullptr;      // cached system rows [n][n_qpad] (lmosem_cache_rows), zero padded
+    bool rows_valid = false;  // Hc holds every row
     int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
     float *col = nullptr;     // surrogate: per-sub-iteration event column features [max_rows][4] + ranks [max_rows][2]
     float *X = nullptr;       // surrogate: network inputs [pair_cap][8]
@@ -150,7 +153,7 @@ void free_set(lmosem_evset *s) {
     drop_graphs(s);
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
-    hipFree(s->H); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
+    hipFree(s->H); hipFree(s->Hc); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
     hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->near); hipFree(s->y); hipFree(s->s.ang);
     delete s;
 }
@@ -244,34 +247,43 @@ hipError_t drain_timing(lmosem_ctx *c) {
 
 // System rows and partial means of subset i: exact forward projection, or
 // exact primaries plus the network's scatter term.
-hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, hipStream_t st) {
+hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStream_t st) {
     const Geo &g = c->g;
     const EvSet &v = s->s;
     const int rows = v.row_off[i + 1] - v.row_off[i];
     if (c->surrogate)
         return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
-                              v.n_real, v.row_off[i], rows, s->H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st);
+                              v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st);
     return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
-                          v.efac, s->f, s->H, s->pmean, v.row_off[i], rows, st);
+                          v.efac, s->f, H, s->pmean, v.row_off[i], rows, st);
 }
 
 int mean_groups(const lmosem_ctx *c) { return c->surrogate ? 1 : forward_groups(c->g); }
 
-// One sub-iteration of Eq. 7 on all realisations of a prepared set.
+// One sub-iteration of Eq. 7 on all realisations of a prepared set: the
+// system rows are computed (and kept when the set caches them) or, once
+// cached, read back for the means.
 hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hipStream_t st) {
     const Geo &g = c->g;
     const EvSet &v = s->s;
     const int rows = v.row_off[i + 1] - v.row_off[i];
     const int n_tiles = v.tile_off[i + 1] - v.tile_off[i];
     const int n_chunks = v.chunk_off[i + 1] - v.chunk_off[i];
-    const int groups = mean_groups(c);
+    const bool cached = s->Hc && s->rows_valid;
+    const int groups = cached ? 1 : mean_groups(c);
+    float *H = s->Hc ? s->Hc + (size_t)v.row_off[i] * g.n_qpad : s->H;
     const float *sens = c->t.sens + (size_t)i * g.n_qpad;
     const int *crange = v.crange + (size_t)i * (v.n_real + 1);
     const int *rrange = v.rrange + (size_t)i * (v.n_real + 1);
     hipError_t e;
-    if ((n_tiles > 0 || (c->surrogate && rows > 0)) &&
-        (e = timed(c, 0, [&] { return forward_rows(c, s, i, st); }, st)) != hipSuccess)
+    if (cached) {
+        if ((e = timed(c, 0, [&] { return launch_row_dot(g, rrange, v.n_real, rows, H, s->f, s->pmean, st); },
+                       st)) != hipSuccess)
+            return e;
+    } else if ((n_tiles > 0 || (c->surrogate && rows > 0)) &&
+               (e = timed(c, 0, [&] { return forward_rows(c, s, i, H, st); }, st)) != hipSuccess) {
         return e;
+    }
     if (rows > 0 &&
         (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, st); }, st)) !=
             hipSuccess)
@@ -280,7 +292,7 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
         return e;
     if (n_chunks > 0 &&
         (e = timed(c, 1, [&] {
-             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, s->H, s->inv, s->pb, st);
+             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, H, s->inv, s->pb, st);
          }, st)) != hipSuccess)
         return e;
     if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, st); }, st)) != hipSuccess)
@@ -312,7 +324,8 @@ hipError_t capture_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
     e = hipStreamEndCapture(c->gst, &graph);
     if (body != hipSuccess) { if (graph) hipGraphDestroy(graph); return body; }
     if (e != hipSuccess) return e;
-    e = hipGraphInstantiate(&s->exec[want_ll ? 1 : 0], graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->exec[(want_ll ? 1 : 0) + (s->Hc && s->rows_valid ? 2 : 0)], graph, nullptr, nullptr,
+                            0);
     hipGraphDestroy(graph);
     return e;
 }
@@ -322,14 +335,17 @@ hipError_t capture_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
 // the caller's stream while kernel timing is on or graphs are disabled.
 hipError_t one_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
     hipError_t e;
-    // the surrogate path allocates network workspace lazily: never captured
-    const bool graph = !c->surrogate && (s->use_graph >= 0 ? s->use_graph == 1 : c->graphs);
+    const bool cached = s->Hc && s->rows_valid;
+    // the surrogate path allocates network workspace lazily: never captured;
+    // the iteration that fills the row cache runs once, uncaptured
+    const bool graph = (!c->surrogate || cached) && !(s->Hc && !cached) &&
+                       (s->use_graph >= 0 ? s->use_graph == 1 : c->graphs);
     if (!graph || c->timing) {
         if (want_ll && (e = launch_fill_d(s->ll, s->s.n_real, 0.0, c->st)) != hipSuccess) return e;
         for (int i = 0; i < c->g.n_subsets; ++i)
             if ((e = subiteration(c, s, i, want_ll, c->st)) != hipSuccess) return e;
     } else {
-        const int k = want_ll ? 1 : 0;
+        const int k = (want_ll ? 1 : 0) + (cached ? 2 : 0);
         if (!s->exec[k] && (e = capture_iteration(c, s, want_ll)) != hipSuccess) return e;
         if ((e = hipEventRecord(c->g_in, c->st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c->gst, c->g_in, 0)) != hipSuccess) return e;
@@ -337,7 +353,8 @@ hipError_t one_iteration(lmosem_ctx *c, lmosem_evset *s, bool want_ll) {
         if ((e = hipEventRecord(c->g_out, c->gst)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c->st, c->g_out, 0)) != hipSuccess) return e;
     }
-    count_terms(c, s);
+    if (!cached) count_terms(c, s);
+    if (s->Hc) s->rows_valid = true;
     return hipSuccess;
 }
 
@@ -565,7 +582,7 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
     const EvSet &v = s->s;
     const int rows = v.row_off[1];
     hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
-    if (e == hipSuccess) e = forward_rows(c, s, 0, c->st);
+    if (e == hipSuccess) e = forward_rows(c, s, 0, s->H, c->st);
     if (e == hipSuccess) e = launch_mean(s->pmean, mean_groups(c), rows, s->mean, s->inv, c->skipped_dev, c->st);
     if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -585,7 +602,7 @@ lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const f
     const EvSet &v = s->s;
     const int rows = v.row_off[1];
     hipError_t e = launch_fill(s->f, (size_t)g.n_qpad, 0.0f, c->st);
-    if (e == hipSuccess) e = forward_rows(c, s, 0, c->st);
+    if (e == hipSuccess) e = forward_rows(c, s, 0, s->H, c->st);
     if (e == hipSuccess) e = launch_gather_rows(weights_dev, v.orig, rows, s->inv, c->st);
     if (e == hipSuccess) e = launch_backproject(g, v.chunks, v.chunk_off[1], s->H, s->inv, s->pb, c->st);
     if (e == hipSuccess) e = launch_sum_real(g, v.crange, 1, s->pb, s->f, c->st);
@@ -693,6 +710,29 @@ lmosem_status lmosem_set_graphs(lmosem_ctx *c, int32_t enable) {
     return LMOSEM_OK;
 }
 
+lmosem_status lmosem_cache_rows(lmosem_ctx *c, lmosem_evset *s, int32_t enable) {
+    GUARD(c);
+    if (!s || s->s.ctx != c) return set_err(c, LMOSEM_EINVAL, "bad event set");
+    drop_graphs(s);
+    s->rows_valid = false;
+    if (!enable) {
+        hipFree(s->Hc);
+        s->Hc = nullptr;
+        return LMOSEM_OK;
+    }
+    if (s->Hc) return LMOSEM_OK;
+    const size_t n = (size_t)std::max<int64_t>(s->s.n, 1) * c->g.n_qpad;
+    hipError_t e = hipMalloc(&s->Hc, sizeof(float) * n);
+    if (e != hipSuccess) {
+        s->Hc = nullptr;
+        (void)hipGetLastError();
+        return set_err(c, LMOSEM_ENOMEM, "row cache: " + std::to_string(sizeof(float) * n) + " bytes not available");
+    }
+    // zero padding columns (the learned-scatter rows never write them)
+    e = launch_fill(s->Hc, n, 0.0f, c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "row cache", e);
+}
+
 }  // extern "C"
 
 namespace {
@@ -761,6 +801,15 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
     const Geo &g = c->g;
     EvSet &v = s->s;
     std::string why, key = tune_key(c, s);
+    // tune the computing path; a row cache is refilled by the next iteration
+    float *hc = s->Hc;
+    s->Hc = nullptr;
+    s->rows_valid = false;
+    struct Restore {
+        lmosem_evset *s;
+        float *hc;
+        ~Restore() { s->Hc = hc; s->rows_valid = false; drop_graphs(s); }
+    } restore{s, hc};
     int best_ev = v.ev_tile, best_ch = v.chunk_rows, best_graph = -1;
     hipError_t e = hipSuccess;
     if (!tune_lookup(key, best_ev, best_ch, best_graph)) {

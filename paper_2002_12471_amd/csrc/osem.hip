@@ -224,6 +224,49 @@ hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean
     return hipGetLastError();
 }
 
+// Cached system rows (the rows do not depend on f): pmean[j] = sum_q
+// f[real(j)][q] H[j][q] over whole padded rows (padding is zero in both).
+// LPR lanes per row (64, or 16 for short rows so that a wave takes four rows
+// at once), float4 loads and a butterfly sum; bound by reading H.
+template <int LPR>
+__global__ __launch_bounds__(256) void k_row_dot(Geo g, const int *__restrict__ rrange, int n_real, int n_rows,
+                                                 const float *__restrict__ H, const float *__restrict__ f,
+                                                 float *__restrict__ pmean) {
+    constexpr int kRowsPerBlock = 256 / LPR;
+    const int sub = threadIdx.x % LPR;
+    const int n4 = g.n_qpad / 4;
+    for (int j = blockIdx.x * kRowsPerBlock + threadIdx.x / LPR; j < n_rows; j += gridDim.x * kRowsPerBlock) {
+        int lo = 0, hi = n_real;   // realisation r with rrange[r] <= j < rrange[r+1]
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (rrange[m] <= j) lo = m; else hi = m; }
+        const float4 *h = reinterpret_cast<const float4 *>(H + (size_t)j * g.n_qpad);
+        const float4 *fr = reinterpret_cast<const float4 *>(f + (size_t)lo * g.n_qpad);
+        float s = 0.0f;
+        for (int k = sub; k < n4; k += LPR) {
+            const float4 x = h[k], y = fr[k];
+            s = fmaf(x.x, y.x, s);
+            s = fmaf(x.y, y.y, s);
+            s = fmaf(x.z, y.z, s);
+            s = fmaf(x.w, y.w, s);
+        }
+#pragma unroll
+        for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (sub == 0) pmean[j] = s;
+    }
+}
+
+hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_rows, const float *H, const float *f,
+                          float *pmean, hipStream_t st) {
+    if (n_rows <= 0) return hipSuccess;
+    if (g.n_qpad / 4 <= 64) {   // rows of at most 256 floats: 16 lanes each
+        const int blocks = std::min((n_rows + 15) / 16, 16384);
+        hipLaunchKernelGGL(k_row_dot<16>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, pmean);
+    } else {
+        const int blocks = std::min((n_rows + 3) / 4, 16384);
+        hipLaunchKernelGGL(k_row_dot<64>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, pmean);
+    }
+    return hipGetLastError();
+}
+
 // pb[c][q] = sum_{j in chunk c} H[j][q] inv[j]; four columns per thread.
 __global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restrict__ chunks,
                                                      const float *__restrict__ H,
@@ -255,23 +298,40 @@ hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, c
     return hipGetLastError();
 }
 
-// f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks.
-__global__ void k_update(Geo g, const int *__restrict__ crange, const float *__restrict__ pb,
-                         const float *__restrict__ sens, float *__restrict__ f) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+// f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks:
+// 64 pixels per block, the chunks split over 4 waves (4 accumulators each)
+// and the wave partials added in a fixed order.
+__global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ crange, const float *__restrict__ pb,
+                                                const float *__restrict__ sens, float *__restrict__ f) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = blockIdx.x * 64 + lane;
     const int r = blockIdx.y;
-    if (q >= g.n_p) return;
-    float b = 0.0f;
-    for (int c = crange[r]; c < crange[r + 1]; ++c) b += pb[(size_t)c * g.n_qpad + q];
-    const float s = sens[q];
-    float *fp = f + (size_t)r * g.n_qpad + q;
-    if (s > 0.0f) *fp = (*fp * b) / s;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (q < g.n_p) {
+        const int c0 = crange[r], c1 = crange[r + 1];
+        int c = c0 + wv;
+        for (; c + 12 < c1; c += 16) {
+            a0 += pb[(size_t)c * g.n_qpad + q];
+            a1 += pb[(size_t)(c + 4) * g.n_qpad + q];
+            a2 += pb[(size_t)(c + 8) * g.n_qpad + q];
+            a3 += pb[(size_t)(c + 12) * g.n_qpad + q];
+        }
+        for (; c < c1; c += 4) a0 += pb[(size_t)c * g.n_qpad + q];
+    }
+    part[wv][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (wv == 0 && q < g.n_p) {
+        const float b = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        const float s = sens[q];
+        float *fp = f + (size_t)r * g.n_qpad + q;
+        if (s > 0.0f) *fp = (*fp * b) / s;
+    }
 }
 
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
                          const float *sens, float *f, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3((g.n_p + 255) / 256, n_real), dim3(256), 0, st, g, crange, pb, sens,
-                       f);
+    hipLaunchKernelGGL(k_update, dim3((g.n_p + 63) / 64, n_real), dim3(256), 0, st, g, crange, pb, sens, f);
     return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ _sigs = {
     "lmosem_autotune": (_S, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
+    "lmosem_cache_rows": (_S, [_P, _P, ctypes.c_int32]),
     "lmosem_net_create": (_S, [_P, _P, ctypes.POINTER(_P)]),
     "lmosem_net_destroy": (None, [_P]),
     "lmosem_net_get_params": (_S, [_P, _P]),
@@ -256,6 +257,10 @@ def lmosem_autotune(ctx, evset) -> tuple:
 
 def lmosem_set_graphs(ctx, enable: bool):
     _check(ctx, _lib.lmosem_set_graphs(ctx, 1 if enable else 0))
+
+
+def lmosem_cache_rows(ctx, evset, enable: bool):
+    _check(ctx, _lib.lmosem_cache_rows(ctx, evset, 1 if enable else 0))
 
 
 def lmosem_measure_alu_rates(stream: torch.cuda.Stream | None = None) -> dict:
