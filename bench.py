@@ -407,7 +407,7 @@ def main():
         bp_s = ks["backproject_ms"] * 1e-3 / max(1, ks["backproject_launches"])
         roof = {
             "bound": "hbm",
-            "kernel": "k_row_dot (event means from cached rows)",
+            "kernel": "k_row_dot (event means and their inverses from cached rows)",
             "achieved": row_bytes / fwd_s / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -417,8 +417,8 @@ def main():
             "units_per_launch": row_bytes / 4,
             "avg_launch_ms": fwd_s * 1e3,
             "backproject_avg_ms": bp_s * 1e3,
-            "backproject_gbps": row_bytes / bp_s / 1e9,
-            "mean_update_avg_ms": ks["update_ms"] / max(1, ks["update_launches"]),
+            "backproject_gbps": row_bytes / bp_s / 1e9 if bp_s > 0 else None,
+            "update_avg_ms": ks["update_ms"] / max(1, ks["update_launches"]),
         }
     else:
         roof = None

@@ -277,14 +277,16 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     const int *rrange = v.rrange + (size_t)i * (v.n_real + 1);
     hipError_t e;
     if (cached) {
-        if ((e = timed(c, 0, [&] { return launch_row_dot(g, rrange, v.n_real, rows, H, s->f, s->pmean, st); },
-                       st)) != hipSuccess)
+        // event means and their inverses straight from the stored rows
+        if ((e = timed(c, 0, [&] {
+                 return launch_row_dot(g, rrange, v.n_real, rows, H, s->f, s->mean, s->inv, c->skipped_dev, st);
+             }, st)) != hipSuccess)
             return e;
     } else if ((n_tiles > 0 || (c->surrogate && rows > 0)) &&
                (e = timed(c, 0, [&] { return forward_rows(c, s, i, H, st); }, st)) != hipSuccess) {
         return e;
     }
-    if (rows > 0 &&
+    if (rows > 0 && !cached &&
         (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, st); }, st)) !=
             hipSuccess)
         return e;

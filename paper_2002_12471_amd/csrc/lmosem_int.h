@@ -97,7 +97,7 @@ hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile
 hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean, float *inv,
                        unsigned long long *skipped, hipStream_t st);
 hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_rows, const float *H, const float *f,
-                          float *pmean, hipStream_t st);
+                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st);
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
                               const float *inv, float *pb, hipStream_t st);
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,

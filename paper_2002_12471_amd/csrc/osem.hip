@@ -224,14 +224,16 @@ hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean
     return hipGetLastError();
 }
 
-// Cached system rows (the rows do not depend on f): pmean[j] = sum_q
-// f[real(j)][q] H[j][q] over whole padded rows (padding is zero in both).
+// Cached system rows (the rows do not depend on f): the event mean
+// mean[j] = sum_q f[real(j)][q] H[j][q] over whole padded rows (padding is zero
+// in both) and its inverse (0, and counted, when the mean is not positive).
 // LPR lanes per row (64, or 16 for short rows so that a wave takes four rows
 // at once), float4 loads and a butterfly sum; bound by reading H.
 template <int LPR>
 __global__ __launch_bounds__(256) void k_row_dot(Geo g, const int *__restrict__ rrange, int n_real, int n_rows,
                                                  const float *__restrict__ H, const float *__restrict__ f,
-                                                 float *__restrict__ pmean) {
+                                                 float *__restrict__ mean, float *__restrict__ inv,
+                                                 unsigned long long *__restrict__ skipped) {
     constexpr int kRowsPerBlock = 256 / LPR;
     const int sub = threadIdx.x % LPR;
     const int n4 = g.n_qpad / 4;
@@ -250,19 +252,26 @@ __global__ __launch_bounds__(256) void k_row_dot(Geo g, const int *__restrict__ 
         }
 #pragma unroll
         for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (sub == 0) pmean[j] = s;
+        if (sub == 0) {
+            const bool dead = !(s > 1e-30f);
+            mean[j] = s;
+            inv[j] = dead ? 0.0f : 1.0f / s;
+            if (dead) atomicAdd(skipped, 1ull);
+        }
     }
 }
 
 hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_rows, const float *H, const float *f,
-                          float *pmean, hipStream_t st) {
+                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     if (g.n_qpad / 4 <= 64) {   // rows of at most 256 floats: 16 lanes each
         const int blocks = std::min((n_rows + 15) / 16, 16384);
-        hipLaunchKernelGGL(k_row_dot<16>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, pmean);
+        hipLaunchKernelGGL(k_row_dot<16>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, mean, inv,
+                           skipped);
     } else {
         const int blocks = std::min((n_rows + 3) / 4, 16384);
-        hipLaunchKernelGGL(k_row_dot<64>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, pmean);
+        hipLaunchKernelGGL(k_row_dot<64>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, mean, inv,
+                           skipped);
     }
     return hipGetLastError();
 }

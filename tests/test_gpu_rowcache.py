@@ -137,3 +137,25 @@ def test_cached_rows_learned_scatter(dev):
     sup = mu.ravel() > 0
     a, b = ref[0].ravel()[sup].astype(np.float64), got[0].ravel()[sup]
     assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4
+
+
+def test_cached_rows_large_support(dev):
+    """A support of 17k pixels (150x150 disk of radius 74 px, 8 angles, rows
+    of 69 KB) with cached rows against the recomputing path."""
+    L = _lib()
+    g = synth.Geometry(150, 150, 0.1, 160, 0.1, 8, n_subsets=2)
+    X, Y = synth.phantoms.pixel_centres(150, 150, 0.1)
+    mu = np.where(X ** 2 + Y ** 2 <= (74 * 0.1) ** 2, 0.15, 0.0).astype(np.float32)
+    act = np.where(X ** 2 + Y ** 2 <= (60 * 0.1) ** 2, 1.0, 0.0).astype(np.float32)
+    assert int((mu > 0).sum()) > 16384
+    ev = synth.generate_events(g, act, mu, 3000, 77)
+    ctx = L.Context(g.as_dict(), torch.as_tensor(mu, device=dev))
+    try:
+        evd = L.events_to_device(ev, dev)
+        ref, _ = _iterate(L, ctx, evd, mu, 3, cache=False)
+        got, _ = _iterate(L, ctx, evd, mu, 3, cache=True, calls=3)
+    finally:
+        ctx.close()
+    sup = mu.ravel() > 0
+    a, b = ref[0].ravel()[sup].astype(np.float64), got[0].ravel()[sup]
+    assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4
