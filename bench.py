@@ -62,12 +62,13 @@ def mix_peak_terms_per_s():
     return N_CU * CLK * FMA_LANES / cyc
 
 
-def profiled_traffic(event_tile, workload):
-    """HBM bytes per forward launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary for this event tile, or None if the kernel source
-    changed since the counters were taken or the tile was not profiled."""
+def profiled_traffic(event_tile, workload, cached=False):
+    """HBM bytes per launch of the dominant kernel (the forward projection at
+    this event tile, or with cached rows the row-dot kernel) from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
+    changed since the counters were taken or the case was not profiled."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_forward_brain64.md")
+    path = os.path.join(ROOT, "profiles", "k_row_dot_brain64_cached.md" if cached else "k_forward_brain64.md")
     src = os.path.join(ROOT, "paper_2002_12471_amd", "csrc", "osem.hip")
     try:
         fields = {}
@@ -76,7 +77,7 @@ def profiled_traffic(event_tile, workload):
                 k, v = line.split(":", 1)
                 fields[k.split(" (")[0].strip()] = v.strip()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        key = f"traffic_bytes_per_launch_ev{event_tile}"
+        key = "traffic_bytes_per_launch_row_dot" if cached else f"traffic_bytes_per_launch_ev{event_tile}"
         if workload != "brain64" or fields.get("source_sha256") != sha or key not in fields:
             return None
         return float(fields[key])
@@ -412,7 +413,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": row_bytes / fwd_s / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": profiled_traffic(tile, args.workload, cached=True),
             "per_unit": "4 bytes per (event, padded support pixel) of the sub-iteration's rows",
             "units_per_launch": row_bytes / 4,
             "avg_launch_ms": fwd_s * 1e3,
