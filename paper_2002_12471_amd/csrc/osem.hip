@@ -36,6 +36,42 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// buffer resource word 3 of the gfx9 family (raw, untyped 32-bit access)
+constexpr int kBufferWord3 = 0x00020000;
+
+// the (alpha, beta) entries of four consecutive ranks of each lane's column
+__device__ __forceinline__ void load_group(__amdgpu_buffer_rsrc_t rs, uint32_t lane_off, uint32_t row0,
+                                           uint32_t rstride, float2 (&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, row0 + i * rstride, 0));
+}
+
+// the terms of four ranks for all EV events: exponent FMA, exp2, accumulate
+template <int EV>
+__device__ __forceinline__ void term_group(const float2 (&v)[4], const float *Kg, const float (&et)[EV],
+                                           float (&acc)[EV]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 *kr = reinterpret_cast<const float4 *>(Kg + i * EV);
+        float4 k4[EV / 4];
+#pragma unroll
+        for (int e4 = 0; e4 < EV / 4; ++e4) k4[e4] = kr[e4];
+        float x[EV];
+#pragma unroll
+        for (int e = 0; e < EV; ++e) x[e] = fmaf(v[i].y, et[e], v[i].x);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) x[e] = __builtin_amdgcn_exp2f(x[e]);
+#pragma unroll
+        for (int e4 = 0; e4 < EV / 4; ++e4) {
+            acc[4 * e4 + 0] = fmaf(k4[e4].x, x[4 * e4 + 0], acc[4 * e4 + 0]);
+            acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
+            acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
+            acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
+        }
+    }
+}
+
 template <int EV>
 __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restrict__ tiles, int n_tiles,
                                              int logical, const float2 *__restrict__ T,
@@ -55,11 +91,14 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         et[e] = e < tl.n ? se[tl.e0 + e] : 0.0f;
         acc[e] = 0.0f;
     }
-    // table slice of this angle: uniform base (SGPRs) plus a 32-bit per-lane
-    // offset, so the loads use the scalar-base addressing form
-    const char *Tbase = reinterpret_cast<const char *>(T + (size_t)tl.angle * g.n_rpad * g.n_qpad);
+    // the table rows of a chunk of ranks as a buffer resource: the per-lane
+    // column offset is the VGPR offset and the rank row the SGPR offset, so a
+    // table load needs no vector address arithmetic; loads past the angle's
+    // rows (the prefetch one group beyond a tile's last rank) return 0 and are
+    // unused
+    const uint32_t rstride = (uint32_t)g.n_qpad * (uint32_t)sizeof(float2);
+    const float2 *Ta = T + (size_t)tl.angle * g.n_rpad * g.n_qpad;
     const uint32_t lane_off = (uint32_t)(wave_on ? q : 0) * (uint32_t)sizeof(float2);
-    const size_t rstride = (size_t)g.n_qpad * sizeof(float2);
     const double *us = us_sorted + (size_t)tl.angle * g.n_p;
     const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
     const float edge = expf(-4.5f);
@@ -81,44 +120,26 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         }
         __syncthreads();
         if (wave_on) {
-            // groups of 4 ranks; the next group's table entries are loaded
-            // while this one is computed.  Ranks past the tile (up to 7) read
-            // the padding rows of the table and meet K' = 0.
+            // groups of 4 ranks in two alternating register sets: the next
+            // group's entries are loaded while this one is computed.  Ranks
+            // past the tile (up to 7) read the padding rows of the table and
+            // meet K' = 0.
             const int n_grp = __builtin_amdgcn_readfirstlane(nr4 >> 2);
-            const char *Tg = Tbase + (size_t)rc * rstride;
-            float2 cur[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                cur[i] = *reinterpret_cast<const float2 *>(Tg + i * rstride + lane_off);
-            for (int gi = 0; gi < n_grp; ++gi) {
-                size_t nxt_off = (size_t)(gi + 1) * 4 * rstride;
-                asm volatile("" : "+s"(nxt_off));   // keep the prefetch where it is
-                float2 nxt[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    nxt[i] = *reinterpret_cast<const float2 *>(Tg + nxt_off + i * rstride + lane_off);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float4 *kr = reinterpret_cast<const float4 *>(Ks + (gi * 4 + i) * EV);
-                    float4 k4[EV / 4];
-#pragma unroll
-                    for (int e4 = 0; e4 < EV / 4; ++e4) k4[e4] = kr[e4];
-                    float x[EV];
-#pragma unroll
-                    for (int e = 0; e < EV; ++e) x[e] = fmaf(cur[i].y, et[e], cur[i].x);
-#pragma unroll
-                    for (int e = 0; e < EV; ++e) x[e] = __builtin_amdgcn_exp2f(x[e]);
-#pragma unroll
-                    for (int e4 = 0; e4 < EV / 4; ++e4) {
-                        acc[4 * e4 + 0] = fmaf(k4[e4].x, x[4 * e4 + 0], acc[4 * e4 + 0]);
-                        acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
-                        acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
-                        acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
+            const uint64_t left = (uint64_t)(g.n_rpad - rc) * rstride;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float2 *>(Ta + (size_t)rc * g.n_qpad), (short)0,
+                (int)(uint32_t)std::min<uint64_t>(left, 0xFFFFFFFFull), kBufferWord3);
+            const uint32_t base = 0;
+            float2 a[4], b[4];
+            load_group(rs, lane_off, base, rstride, a);
+            int gi = 0;
+            for (; gi + 1 < n_grp; gi += 2) {
+                load_group(rs, lane_off, base + (uint32_t)(gi + 1) * 4u * rstride, rstride, b);
+                term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
+                load_group(rs, lane_off, base + (uint32_t)(gi + 2) * 4u * rstride, rstride, a);
+                term_group<EV>(b, Ks + (gi + 1) * 4 * EV, et, acc);
             }
+            if (gi < n_grp) term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
         }
     }
 
