@@ -244,6 +244,34 @@ lmosem_status lmosem_set_graphs(lmosem_ctx *ctx, int32_t enable);
  * set stays usable without the cache), EINVAL. */
 lmosem_status lmosem_cache_rows(lmosem_ctx *ctx, lmosem_evset *set, int32_t enable);
 
+/* ---- binned data (the binned alternative of Sec. 2.2) ----------------
+ * Bins (a, b, k): detector angle a, position bin b of n_pos equal bins over
+ * the detector, energy bin k = [e_edges[k], e_edges[k+1]) (the last bin
+ * includes its upper edge); flat index (a * n_pos + b) * n_ebins + k.  e_edges
+ * is a host array of n_ebins + 1 increasing energies (keV).  The binned
+ * system row of a bin is the integral of the list-mode row h (Eq. 2, 8) over
+ * the bin, from closed-form position and energy masses with every path
+ * weight in FP64. */
+
+/* counts_dev[n_angles][n_pos][n_ebins] = number of events in each bin (the
+ * array is overwritten; events outside every bin are not counted). */
+lmosem_status lmosem_bin_events(lmosem_ctx *ctx, const lmosem_events *ev, int32_t n_pos, const double *e_edges,
+                                int32_t n_ebins, float *counts_dev);
+/* rows_dev[n][ny][nx] = the binned system rows of the n bins listed in
+ * bins_dev (flat indices; 0 off the support).  Errors: ERANGE for a bin
+ * index out of range. */
+lmosem_status lmosem_binned_rows(lmosem_ctx *ctx, int32_t n_pos, const double *e_edges, int32_t n_ebins, int64_t n,
+                                 const int32_t *bins_dev, float *rows_dev);
+/* Binned OS-MLEM (Eq. 7 with counts): subsets by detector angle as in list
+ * mode; each sub-iteration f <- f * H_i^T (y_i / H_i f) / H_i^T 1 over the
+ * subset's bins (bins with zero mean are left out).  counts_dev as written by
+ * lmosem_bin_events; init_dev (nullable: 1 on the support) and image_dev are
+ * [ny][nx].  Allocates its rows (n_angles * n_pos * n_ebins x padded support
+ * floats) for the call; ENOMEM if they do not fit. */
+lmosem_status lmosem_binned_reconstruct(lmosem_ctx *ctx, int32_t n_pos, const double *e_edges, int32_t n_ebins,
+                                        const float *counts_dev, int32_t n_iters, const float *init_dev,
+                                        float *image_dev);
+
 /* Counters of this context (synchronises the context's stream). */
 lmosem_status lmosem_get_stats(const lmosem_ctx *ctx, lmosem_stats *out);
 

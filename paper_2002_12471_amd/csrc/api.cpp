@@ -712,6 +712,159 @@ lmosem_status lmosem_set_graphs(lmosem_ctx *c, int32_t enable) {
     return LMOSEM_OK;
 }
 
+namespace {
+
+// validation of a binning; the energy edges go to the device
+lmosem_status binning(lmosem_ctx *c, int32_t n_pos, const double *edges, int32_t n_e, double **edges_dev) {
+    if (n_pos < 1 || n_e < 1 || !edges) return set_err(c, LMOSEM_EINVAL, "bad binning");
+    for (int k = 0; k < n_e; ++k)
+        if (!(edges[k + 1] > edges[k]) || !std::isfinite(edges[k]) || !std::isfinite(edges[k + 1]))
+            return set_err(c, LMOSEM_EINVAL, "energy edges must increase");
+    if ((int64_t)c->g.n_angles * n_pos * n_e > (1 << 26)) return set_err(c, LMOSEM_ERANGE, "too many bins");
+    hipError_t e = hipMalloc(edges_dev, sizeof(double) * (n_e + 1));
+    if (e == hipSuccess) e = hipMemcpyAsync(*edges_dev, edges, sizeof(double) * (n_e + 1), hipMemcpyHostToDevice, c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "binning", e);
+}
+
+}  // namespace
+
+lmosem_status lmosem_bin_events(lmosem_ctx *c, const lmosem_events *ev, int32_t n_pos, const double *e_edges,
+                                int32_t n_ebins, float *counts_dev) {
+    GUARD(c);
+    if (!counts_dev) return set_err(c, LMOSEM_EINVAL, "bad counts");
+    lmosem_status st = LMOSEM_OK;
+    if (!check_events(c, ev, st)) return st;
+    double *edges = nullptr;
+    if ((st = binning(c, n_pos, e_edges, n_ebins, &edges)) != LMOSEM_OK) { hipFree(edges); return st; }
+    const size_t n_cnt = (size_t)c->g.n_angles * n_pos * n_ebins;
+    hipError_t e = launch_fill(counts_dev, n_cnt, 0.0f, c->st);
+    if (e == hipSuccess) e = launch_bin_events(c->g, *ev, n_pos, edges, n_ebins, counts_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(edges);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "bin events", e);
+}
+
+lmosem_status lmosem_binned_rows(lmosem_ctx *c, int32_t n_pos, const double *e_edges, int32_t n_ebins, int64_t n,
+                                 const int32_t *bins_dev, float *rows_dev) {
+    GUARD(c);
+    if (n < 0 || n > (1 << 24) || (n > 0 && (!bins_dev || !rows_dev))) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    if (n == 0) return LMOSEM_OK;
+    const Geo &g = c->g;
+    std::vector<int32_t> bins(n);
+    hipError_t e = hipMemcpyAsync(bins.data(), bins_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return dev_err(c, "binned rows", e);
+    const int64_t n_all = (int64_t)g.n_angles * n_pos * n_ebins;
+    for (int32_t b : bins)
+        if (b < 0 || b >= n_all) return set_err(c, LMOSEM_ERANGE, "bin index out of range");
+    double *edges = nullptr;
+    lmosem_status st = binning(c, n_pos, e_edges, n_ebins, &edges);
+    if (st != LMOSEM_OK) { hipFree(edges); return st; }
+    float *H = nullptr;
+    e = hipMalloc(&H, sizeof(float) * (size_t)n * g.n_qpad);
+    if (e == hipSuccess)
+        e = launch_binned_rows(g, c->t, n_pos, edges, n_ebins, reinterpret_cast<const int *>(bins_dev), (int)n, H, c->st);
+    if (e == hipSuccess) e = launch_scatter_image(g, c->t, H, (int)n, rows_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(H);
+    hipFree(edges);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "binned rows", e);
+}
+
+lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const double *e_edges, int32_t n_ebins,
+                                        const float *counts_dev, int32_t n_iters, const float *init_dev,
+                                        float *image_dev) {
+    GUARD(c);
+    if (!counts_dev || !image_dev || n_iters < 0) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    const Geo &g = c->g;
+    double *edges = nullptr;
+    lmosem_status st = binning(c, n_pos, e_edges, n_ebins, &edges);
+    if (st != LMOSEM_OK) { hipFree(edges); return st; }
+    // rows ordered by subset, then angle, position bin and energy bin
+    const int per_angle = n_pos * n_ebins;
+    std::vector<int> row_bin, sub_off(g.n_subsets + 1, 0), chunk_off(g.n_subsets + 1, 0);
+    std::vector<Chunk> chunks;
+    std::vector<int> cr;   // per subset {0, n_chunks}
+    const int kRows = 256;
+    for (int i = 0; i < g.n_subsets; ++i) {
+        sub_off[i] = (int)row_bin.size();
+        for (int a = i; a < g.n_angles; a += g.n_subsets)
+            for (int k = 0; k < per_angle; ++k) row_bin.push_back(a * per_angle + k);
+        const int rows = (int)row_bin.size() - sub_off[i];
+        chunk_off[i] = (int)chunks.size();
+        for (int j0 = 0; j0 < rows; j0 += kRows) chunks.push_back(Chunk{j0, std::min(rows, j0 + kRows), 0, 0});
+        cr.push_back(0);
+        cr.push_back((int)chunks.size() - chunk_off[i]);
+    }
+    sub_off[g.n_subsets] = (int)row_bin.size();
+    chunk_off[g.n_subsets] = (int)chunks.size();
+    const int n_rows = (int)row_bin.size();
+    int max_rows = 0, max_chunks = 0;
+    for (int i = 0; i < g.n_subsets; ++i) {
+        max_rows = std::max(max_rows, sub_off[i + 1] - sub_off[i]);
+        max_chunks = std::max(max_chunks, chunk_off[i + 1] - chunk_off[i]);
+    }
+    std::vector<int> rr;   // per subset {0, rows}
+    for (int i = 0; i < g.n_subsets; ++i) { rr.push_back(0); rr.push_back(sub_off[i + 1] - sub_off[i]); }
+
+    float *H = nullptr, *y = nullptr, *mean = nullptr, *inv = nullptr, *w = nullptr, *ones = nullptr, *pb = nullptr;
+    float *sens = nullptr, *f = nullptr;
+    int *d_rows = nullptr, *d_cr = nullptr, *d_rr = nullptr;
+    Chunk *d_chunks = nullptr;
+    unsigned long long *dead = nullptr;
+    hipError_t e = hipSuccess;
+    auto al = [&](void **p, size_t bytes) { if (e == hipSuccess) e = hipMalloc(p, bytes); };
+    al((void **)&H, sizeof(float) * (size_t)n_rows * g.n_qpad);
+    al((void **)&y, sizeof(float) * n_rows);
+    al((void **)&mean, sizeof(float) * max_rows);
+    al((void **)&inv, sizeof(float) * max_rows);
+    al((void **)&w, sizeof(float) * max_rows);
+    al((void **)&ones, sizeof(float) * max_rows);
+    al((void **)&pb, sizeof(float) * (size_t)std::max(max_chunks, 1) * g.n_qpad);
+    al((void **)&sens, sizeof(float) * (size_t)g.n_subsets * g.n_qpad);
+    al((void **)&f, sizeof(float) * g.n_qpad);
+    al((void **)&d_rows, sizeof(int) * n_rows);
+    al((void **)&d_cr, sizeof(int) * cr.size());
+    al((void **)&d_rr, sizeof(int) * rr.size());
+    al((void **)&d_chunks, sizeof(Chunk) * std::max<size_t>(chunks.size(), 1));
+    al((void **)&dead, sizeof(unsigned long long));
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st);
+    };
+    up(d_rows, row_bin.data(), sizeof(int) * n_rows);
+    up(d_cr, cr.data(), sizeof(int) * cr.size());
+    up(d_rr, rr.data(), sizeof(int) * rr.size());
+    up(d_chunks, chunks.data(), sizeof(Chunk) * chunks.size());
+    if (e == hipSuccess) e = launch_fill(ones, max_rows, 1.0f, c->st);
+    if (e == hipSuccess) e = launch_binned_rows(g, c->t, n_pos, edges, n_ebins, d_rows, n_rows, H, c->st);
+    if (e == hipSuccess) e = launch_gather_counts(counts_dev, d_rows, n_rows, y, c->st);
+    // the binned sensitivity of each subset: column sums of its rows
+    for (int i = 0; i < g.n_subsets && e == hipSuccess; ++i) {
+        const float *Hi = H + (size_t)sub_off[i] * g.n_qpad;
+        e = launch_backproject(g, d_chunks + chunk_off[i], chunk_off[i + 1] - chunk_off[i], Hi, ones, pb, c->st);
+        if (e == hipSuccess) e = launch_sum_real(g, d_cr + 2 * i, 1, pb, sens + (size_t)i * g.n_qpad, c->st);
+    }
+    if (e == hipSuccess) e = launch_gather_image(g, c->t, init_dev, 1, 0, f, 0, c->st);
+    for (int it = 0; it < n_iters && e == hipSuccess; ++it)
+        for (int i = 0; i < g.n_subsets && e == hipSuccess; ++i) {
+            const int rows = sub_off[i + 1] - sub_off[i];
+            const float *Hi = H + (size_t)sub_off[i] * g.n_qpad;
+            e = launch_row_dot(g, d_rr + 2 * i, 1, rows, Hi, f, mean, inv, dead, c->st);
+            if (e == hipSuccess) e = launch_count_weights(y + sub_off[i], inv, rows, w, c->st);
+            if (e == hipSuccess)
+                e = launch_backproject(g, d_chunks + chunk_off[i], chunk_off[i + 1] - chunk_off[i], Hi, w, pb, c->st);
+            if (e == hipSuccess) e = launch_update(g, d_cr + 2 * i, 1, pb, sens + (size_t)i * g.n_qpad, f, c->st);
+        }
+    if (e == hipSuccess) e = launch_scatter_image(g, c->t, f, 1, image_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    for (void *p : {(void *)H, (void *)y, (void *)mean, (void *)inv, (void *)w, (void *)ones, (void *)pb, (void *)sens,
+                    (void *)f, (void *)d_rows, (void *)d_cr, (void *)d_rr, (void *)d_chunks, (void *)dead,
+                    (void *)edges})
+        hipFree(p);
+    if (e == hipErrorOutOfMemory) { (void)hipGetLastError(); return set_err(c, LMOSEM_ENOMEM, "binned reconstruction: out of memory"); }
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "binned reconstruction", e);
+}
+
 lmosem_status lmosem_cache_rows(lmosem_ctx *c, lmosem_evset *s, int32_t enable) {
     GUARD(c);
     if (!s || s->s.ctx != c) return set_err(c, LMOSEM_EINVAL, "bad event set");

@@ -65,8 +65,9 @@ struct Tables {
     float *Ldet = nullptr;       // [n_angles][n_p] attenuation from the pixel centre to the detector
     float *Lback = nullptr;      // [n_angles][n_p] attenuation from the pixel centre away from it
     float *prim = nullptr;       // [n_angles][n_p] alpha of each pixel's primary path
-    // scatter contexts: per-angle line integrals and scatter-point factors,
-    // kept for exact path weights evaluated on the fly (training targets)
+    // per-angle line integrals (every context) and scatter-point factors
+    // (scatter contexts), kept for path weights evaluated on the fly
+    // (training targets, binned rows)
     double *Ld = nullptr;        // [n_angles][n_p] L_a(p)
     double *Bt = nullptr;        // [n_p][n_p] B(q, s) at [s][q]
     // learned-scatter contexts: exact near-field paths of each emission pixel
@@ -88,6 +89,14 @@ hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
                        hipStream_t st, std::string &err);
 hipError_t plan_tiles(const Geo &g, const Tables &t, EvSet &set, int ev_tile, int chunk_rows,
                       hipStream_t st, std::string &err);
+
+// ---- binned data (binned.hip) ----
+hipError_t launch_binned_rows(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,
+                              const int *row_bin_dev, int n_rows, float *H, hipStream_t st);
+hipError_t launch_bin_events(const Geo &g, const lmosem_events &ev, int n_pos, const double *edges_dev, int n_e,
+                             float *counts, hipStream_t st);
+hipError_t launch_gather_counts(const float *counts, const int *row_bin, int n_rows, float *y, hipStream_t st);
+hipError_t launch_count_weights(const float *y, const float *inv, int n_rows, float *w, hipStream_t st);
 
 // ---- per sub-iteration kernels (osem.hip) ----
 int forward_groups(const Geo &g);

@@ -305,11 +305,14 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
                        t.sens, t.sens_all);
     CK(hipGetLastError(), "sensitivity");
     CK(hipStreamSynchronize(st), "table build");
-    if (g.scatter) {   // kept for on-the-fly path weights
-        t.Ld = L;
+    // kept for path weights evaluated on the fly (training targets, binned rows)
+    t.Ld = L;
+    L = nullptr;
+    bytes += (int64_t)(sizeof(double) * (size_t)g.n_angles * g.n_p);
+    if (g.scatter) {
         t.Bt = Bt;
-        bytes += (int64_t)(sizeof(double) * ((size_t)g.n_angles * g.n_p + (size_t)g.n_p * g.n_p));
-        L = Bt = nullptr;
+        Bt = nullptr;
+        bytes += (int64_t)(sizeof(double) * (size_t)g.n_p * g.n_p);
     }
     hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
 #undef CK

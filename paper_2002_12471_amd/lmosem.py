@@ -87,6 +87,9 @@ _sigs = {
                             ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
     "lmosem_cache_rows": (_S, [_P, _P, ctypes.c_int32]),
+    "lmosem_bin_events": (_S, [_P, ctypes.POINTER(lmosem_events), ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "lmosem_binned_rows": (_S, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int64, _P, _P]),
+    "lmosem_binned_reconstruct": (_S, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "lmosem_net_create": (_S, [_P, _P, ctypes.POINTER(_P)]),
     "lmosem_net_destroy": (None, [_P]),
     "lmosem_net_get_params": (_S, [_P, _P]),
@@ -261,6 +264,33 @@ def lmosem_set_graphs(ctx, enable: bool):
 
 def lmosem_cache_rows(ctx, evset, enable: bool):
     _check(ctx, _lib.lmosem_cache_rows(ctx, evset, 1 if enable else 0))
+
+
+def _edges(e_edges):
+    return np.ascontiguousarray(e_edges, np.float64)
+
+
+def lmosem_bin_events(ctx, events: dict, n_pos: int, e_edges, counts_out: torch.Tensor):
+    ev = _events(events)
+    ed = _edges(e_edges)
+    _check(ctx, _lib.lmosem_bin_events(ctx, ctypes.byref(ev), int(n_pos), ed.ctypes.data, len(ed) - 1,
+                                       _dev_ptr(counts_out, torch.float32, "counts")))
+
+
+def lmosem_binned_rows(ctx, n_pos: int, e_edges, bins: torch.Tensor, rows_out: torch.Tensor):
+    ed = _edges(e_edges)
+    _check(ctx, _lib.lmosem_binned_rows(ctx, int(n_pos), ed.ctypes.data, len(ed) - 1, int(bins.numel()),
+                                        _dev_ptr(bins, torch.int32, "bins"),
+                                        _dev_ptr(rows_out, torch.float32, "rows")))
+
+
+def lmosem_binned_reconstruct(ctx, n_pos: int, e_edges, counts: torch.Tensor, n_iters: int,
+                              image_out: torch.Tensor, init: torch.Tensor | None = None):
+    ed = _edges(e_edges)
+    _check(ctx, _lib.lmosem_binned_reconstruct(ctx, int(n_pos), ed.ctypes.data, len(ed) - 1,
+                                               _dev_ptr(counts, torch.float32, "counts"), int(n_iters),
+                                               _dev_ptr(init, torch.float32, "init"),
+                                               _dev_ptr(image_out, torch.float32, "image")))
 
 
 def lmosem_measure_alu_rates(stream: torch.cuda.Stream | None = None) -> dict:

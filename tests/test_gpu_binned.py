@@ -1,0 +1,117 @@
+"""GPU tests of the binned alternative: binned system rows against the
+oracle's closed-form box probability, bins that tile the detector and window
+against the list-mode sensitivity, event binning against a plain histogram,
+and binned OS-MLEM against the oracle's binned OS-MLEM."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+import synth  # noqa: E402
+
+EDGES = [100.0, 143.0, 175.0]
+N_POS = 8
+
+
+def _lib():
+    from paper_2002_12471_amd import lmosem as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def tiny(dev):
+    w = synth.workload("tiny")
+    g = dict(w.geom.as_dict(), n_subsets=4)
+    act, mu = synth.phantom(w)
+    return dict(g=g, act=act, mu=mu, ev=synth.workload_events(w), m=O.OracleModel(g, mu))
+
+
+def _rows(L, ctx, bins, dev, mu, edges=EDGES, n_pos=N_POS):
+    out = torch.empty((len(bins),) + mu.shape, device=dev)
+    L.lmosem_binned_rows(ctx.handle, n_pos, edges, torch.as_tensor(np.asarray(bins, np.int32), device=dev), out)
+    return out.cpu().numpy().reshape(len(bins), -1)
+
+
+@pytest.mark.parametrize("scatter_model", [1, 0])
+def test_binned_rows_match_oracle(tiny, dev, scatter_model):
+    L = _lib()
+    g, mu, m = tiny["g"], tiny["mu"], tiny["m"]
+    ctx = L.Context(dict(g, scatter_model=scatter_model), torch.as_tensor(mu, device=dev))
+    try:
+        bins = np.sort(np.random.default_rng(1).choice(16 * N_POS * 2, 40, replace=False))
+        got = _rows(L, ctx, bins, dev, mu)
+    finally:
+        ctx.close()
+    mo = m if scatter_model == 1 else O.OracleModel(g, mu, scatter=0)
+    half = 0.5 * g["n_bins"] * g["bin_cm"]
+    width = 2 * half / N_POS
+    for i, b in enumerate(bins):
+        a, pb, k = b // (N_POS * 2), (b // 2) % N_POS, b % 2
+        ref = mo.box_sums([a], -half + pb * width, -half + (pb + 1) * width, EDGES[k], EDGES[k + 1])
+        g_sup = got[i][mo.support]
+        np.testing.assert_allclose(g_sup, ref, rtol=1e-5, atol=1e-7 * max(ref.max(), 1e-30))
+        assert np.all(np.delete(got[i], mo.support) == 0)
+
+
+def test_binned_rows_tile_the_sensitivity(tiny, dev):
+    """All bins of subset 1's angles over the whole detector and window: their
+    column sums equal the list-mode sensitivity of that subset."""
+    L = _lib()
+    g, mu = tiny["g"], tiny["mu"]
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+    try:
+        bins = [(a * N_POS + b) * 2 + k for a in (1, 5, 9, 13) for b in range(N_POS) for k in range(2)]
+        got = _rows(L, ctx, bins, dev, mu).sum(axis=0)
+        sens = ctx.sensitivity(1).cpu().numpy().ravel()
+    finally:
+        ctx.close()
+    sup = mu.ravel() > 0
+    np.testing.assert_allclose(got[sup], sens[sup], rtol=2e-5)
+
+
+def test_bin_events_matches_histogram(tiny, dev):
+    L = _lib()
+    g, mu, ev = tiny["g"], tiny["mu"], tiny["ev"]
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+    try:
+        counts = torch.empty(16 * N_POS * 2, device=dev)
+        L.lmosem_bin_events(ctx.handle, L.events_to_device(ev, dev), N_POS, EDGES, counts)
+        got = counts.cpu().numpy()
+    finally:
+        ctx.close()
+    b = np.minimum((ev["u_bin"].astype(np.float64) * N_POS / g["n_bins"]).astype(int), N_POS - 1)
+    k = (ev["energy"] >= EDGES[1]).astype(int)
+    ref = np.bincount((ev["angle"] * N_POS + b) * 2 + k, minlength=16 * N_POS * 2)
+    np.testing.assert_array_equal(got, ref)
+    assert got.sum() == len(ev["angle"])
+
+
+def test_binned_reconstruct_matches_oracle(tiny, dev):
+    """8 position bins x 2 energy bins, 4 subsets, 5 iterations."""
+    L = _lib()
+    g, mu, ev, m = tiny["g"], tiny["mu"], tiny["ev"], tiny["m"]
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+    try:
+        counts = torch.empty(16 * N_POS * 2, device=dev)
+        L.lmosem_bin_events(ctx.handle, L.events_to_device(ev, dev), N_POS, EDGES, counts)
+        img = torch.empty(mu.shape, device=dev)
+        L.lmosem_binned_reconstruct(ctx.handle, N_POS, EDGES, counts, 5, img)
+        got = img.cpu().numpy().ravel()[m.support]
+        y = counts.cpu().numpy().astype(np.float64)
+    finally:
+        ctx.close()
+    H = O.binned_rows(m, N_POS, EDGES)
+    row_angle = np.repeat(np.arange(16), N_POS * 2)
+    ref = O.binned_os_mlem(H, y, row_angle, 4, 5, np.ones(len(m.support)))
+    err = np.abs(got - ref)
+    tol = np.where(ref >= 1e-2 * ref.max(), 1e-3 * ref, 1e-5 * ref.max())
+    assert np.all(err <= tol), float(np.max(err / np.maximum(ref, 1e-300)))
