@@ -732,8 +732,10 @@ lmosem_status lmosem_bin_events(lmosem_ctx *c, const lmosem_events *ev, int32_t 
                                 int32_t n_ebins, float *counts_dev) {
     GUARD(c);
     if (!counts_dev) return set_err(c, LMOSEM_EINVAL, "bad counts");
+    // events outside every bin (any angle, position or energy) are dropped
+    if (!ev || ev->n < 0 || (ev->n > 0 && (!ev->angle || !ev->u_bin || !ev->energy_kev)))
+        return set_err(c, LMOSEM_EINVAL, "bad event arrays");
     lmosem_status st = LMOSEM_OK;
-    if (!check_events(c, ev, st)) return st;
     double *edges = nullptr;
     if ((st = binning(c, n_pos, e_edges, n_ebins, &edges)) != LMOSEM_OK) { hipFree(edges); return st; }
     const size_t n_cnt = (size_t)c->g.n_angles * n_pos * n_ebins;

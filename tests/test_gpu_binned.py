@@ -115,3 +115,18 @@ def test_binned_reconstruct_matches_oracle(tiny, dev):
     err = np.abs(got - ref)
     tol = np.where(ref >= 1e-2 * ref.max(), 1e-3 * ref, 1e-5 * ref.max())
     assert np.all(err <= tol), float(np.max(err / np.maximum(ref, 1e-300)))
+
+
+def test_bin_events_drops_events_outside_the_bins(tiny, dev):
+    """Photopeak-only bins on whole-spectrum events: only the events inside
+    [143, 175] keV are counted."""
+    L = _lib()
+    g, mu, ev = tiny["g"], tiny["mu"], tiny["ev"]
+    ctx = L.Context(dict(g, win_lo_kev=143.0), torch.as_tensor(mu, device=dev))
+    try:
+        counts = torch.empty(16 * N_POS, device=dev)
+        L.lmosem_bin_events(ctx.handle, L.events_to_device(ev, dev), N_POS, [143.0, 175.0], counts)
+        got = counts.cpu().numpy()
+    finally:
+        ctx.close()
+    assert got.sum() == int((ev["energy"] >= 143.0).sum())
