@@ -24,8 +24,9 @@
  * Conventions
  *   image      float32, row-major [ny][nx], pixel (i, j) centred at
  *              ((i - (nx-1)/2) pixel_cm, (j - (ny-1)/2) pixel_cm).  Activity is
- *              estimated on the mu > 0 support (the emission set); outputs are
- *              0 elsewhere and inputs are ignored there.
+ *              estimated on the emission set: the mu > 0 support, or the part
+ *              of it a mask selects (lmosem_create_emission); outputs are 0
+ *              elsewhere and inputs are ignored there.
  *   angle      theta_a = angle0_rad + 2 pi a / n_angles, a in [0, n_angles);
  *              photons reach the detector travelling along (cos, sin) theta_a.
  *   position   u_bin in [0, n_bins): u = (u_bin - n_bins/2) bin_cm along
@@ -113,7 +114,7 @@ typedef struct {
 
 /* Per-context counters, filled by lmosem_get_stats. */
 typedef struct {
-    int64_t n_support;          /* pixels with mu > 0 (emission and scatter set) */
+    int64_t n_support;          /* pixels with mu > 0 (path ends and scatter points) */
     int64_t skipped_events;     /* events whose model mean was <= 1e-30, since create */
     int64_t inner_terms;        /* (event, emission pixel, path end) terms evaluated by
                                    the forward projection, since create */
@@ -121,7 +122,7 @@ typedef struct {
     double table_ms;            /* time of the table build in lmosem_create */
     int64_t table_bytes;        /* device bytes held by the path tables */
     int32_t event_tile;         /* events per forward-projection tile */
-    int32_t reserved;
+    int32_t n_emission;         /* emission pixels (the estimated image), <= n_support */
     /* kernel times from HIP events on the context's stream, recorded only
        while timing is enabled (lmosem_set_timing) */
     int64_t forward_launches;
@@ -145,6 +146,18 @@ uint32_t lmosem_abi_version(void);
  * Errors: EINVAL (config), ERANGE (mu), ENOMEM, EDEVICE. */
 lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void *hip_stream,
                             lmosem_ctx **out);
+
+/* As lmosem_create, with the estimated image restricted to an emission set
+ * (Sec. 2.2: the work of every iteration scales with the number of non-zero
+ * pixels, so the initial estimate is confined to a crude object boundary,
+ * e.g. from a binned OS-MLEM).  emission_dev: [ny][nx] float32, device,
+ * nullable; the emission set is {mu > 0 and emission > 0} (NULL: mu > 0).
+ * Scatter points and path ends stay the whole mu > 0 support, so the model
+ * of the remaining emission pixels is unchanged.  Images written by the
+ * context are 0 outside the emission set; images read by it are read only
+ * on it.  Errors: as lmosem_create; ERANGE also for an empty emission set. */
+lmosem_status lmosem_create_emission(const lmosem_config *cfg, const float *mu_dev, const float *emission_dev,
+                                     void *hip_stream, lmosem_ctx **out);
 
 /* Free the context and everything it owns (NULL is a no-op). */
 void lmosem_destroy(lmosem_ctx *ctx);
@@ -184,7 +197,7 @@ lmosem_status lmosem_subset_update(lmosem_ctx *ctx, int32_t subset, const lmosem
 
 /* Full OS-LM-MLEM (Eq. 7-9): n_iters global iterations over all subsets in
  * order, for one realisation (batch NULL) or several independent ones.
- * init_dev (nullable: 1 on the support) is [ny][nx], shared by all
+ * init_dev (nullable: 1 on the emission set) is [ny][nx], shared by all
  * realisations; images_dev [n_real][ny][nx] receives the estimates.
  * loglik_host (nullable) [n_real][n_iters] receives, per global iteration,
  * sum_i (sum_{j in S_i} log mean_j - sum_q f_q sens_q^(i)) at the estimate
@@ -205,7 +218,7 @@ void lmosem_events_free(lmosem_evset *set);
 
 /* n_iters global iterations on a prepared set; images_dev [n_real][ny][nx]
  * is the starting estimate on entry and the result on return (values
- * outside the support are set to 0).  loglik_host as in lmosem_reconstruct
+ * outside the emission set are set to 0).  loglik_host as in lmosem_reconstruct
  * (nullable; if given the call synchronises). */
 lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters,
                              float *images_dev, double *loglik_host);
@@ -220,7 +233,7 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
  * replayed as a HIP graph; re-plans the set with the fastest choices and
  * returns them (outputs may be NULL).  With LMOSEM_TUNE_CACHE=<file> in the
  * environment the choice is looked up in / appended to that file, keyed by
- * support size, angles, subsets, realisations and subset size.  Results do
+ * support and emission-set sizes, angles, subsets, realisations and subset size.  Results do
  * not depend on the choice beyond FP32 summation order.  Synchronises. */
 lmosem_status lmosem_autotune(lmosem_ctx *ctx, lmosem_evset *set, int32_t *event_tile,
                               int32_t *chunk_rows, int32_t *use_graphs);
@@ -235,7 +248,7 @@ lmosem_status lmosem_set_graphs(lmosem_ctx *ctx, int32_t enable);
 /* Keep the system rows of a prepared set across iterations (enable = 1) or
  * stop (0).  The rows h_j(q) do not depend on the estimate (Eq. 8 divides
  * them only by the event means), so after one iteration has computed and
- * stored all of them (n events x padded support x 4 bytes, allocated here,
+ * stored all of them (n events x padded emission set x 4 bytes, allocated here,
  * owned by the set, zero-filled), every later sub-iteration reads them twice
  * from HBM (the event means, then the backprojection of Eq. 7) instead of
  * recomputing every path term.  Results equal the recomputing path up to
@@ -258,19 +271,32 @@ lmosem_status lmosem_cache_rows(lmosem_ctx *ctx, lmosem_evset *set, int32_t enab
 lmosem_status lmosem_bin_events(lmosem_ctx *ctx, const lmosem_events *ev, int32_t n_pos, const double *e_edges,
                                 int32_t n_ebins, float *counts_dev);
 /* rows_dev[n][ny][nx] = the binned system rows of the n bins listed in
- * bins_dev (flat indices; 0 off the support).  Errors: ERANGE for a bin
+ * bins_dev (flat indices; 0 off the emission set).  Errors: ERANGE for a bin
  * index out of range. */
 lmosem_status lmosem_binned_rows(lmosem_ctx *ctx, int32_t n_pos, const double *e_edges, int32_t n_ebins, int64_t n,
                                  const int32_t *bins_dev, float *rows_dev);
 /* Binned OS-MLEM (Eq. 7 with counts): subsets by detector angle as in list
  * mode; each sub-iteration f <- f * H_i^T (y_i / H_i f) / H_i^T 1 over the
  * subset's bins (bins with zero mean are left out).  counts_dev as written by
- * lmosem_bin_events; init_dev (nullable: 1 on the support) and image_dev are
- * [ny][nx].  Allocates its rows (n_angles * n_pos * n_ebins x padded support
+ * lmosem_bin_events; init_dev (nullable: 1 on the emission set) and image_dev are
+ * [ny][nx].  Allocates its rows (n_angles * n_pos * n_ebins x padded emission set
  * floats) for the call; ENOMEM if they do not fit. */
 lmosem_status lmosem_binned_reconstruct(lmosem_ctx *ctx, int32_t n_pos, const double *e_edges, int32_t n_ebins,
                                         const float *counts_dev, int32_t n_iters, const float *init_dev,
                                         float *image_dev);
+
+/* Emission set from a crude image (Sec. 2.2: a rough object boundary from a
+ * quick binned OS-MLEM keeps the number of estimated pixels small):
+ *   mask[p] = 1 if mu[p] > 0 and a pixel p' within margin_px pixels of p
+ *             ((di^2 + dj^2) <= margin_px^2) has
+ *             image[p'] >= rel_threshold * max(image), in FP64;
+ *   mask[p] = 0 otherwise.
+ * mu is this context's map.  image_dev, mask_dev: [ny][nx] float32, device;
+ * the mask is meant for lmosem_create_emission.  rel_threshold in [0, 1],
+ * margin_px in [0, 32].  Synchronises.  Errors: EINVAL (arguments), ERANGE
+ * (image values negative or not finite). */
+lmosem_status lmosem_emission_mask(lmosem_ctx *ctx, const float *image_dev, double rel_threshold, int32_t margin_px,
+                                   float *mask_dev);
 
 /* Counters of this context (synchronises the context's stream). */
 lmosem_status lmosem_get_stats(const lmosem_ctx *ctx, lmosem_stats *out);
@@ -323,13 +349,13 @@ lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const flo
  * receives each epoch's mean loss. */
 lmosem_status lmosem_net_train(lmosem_net *net, const float *X_dev, const float *t_dev, int64_t n, int32_t batch,
                                int32_t epochs, float lr, float lr_decay, double *loss_host);
-/* Training samples on a scatter_model-1 or -2 context: for each (support
+/* Training samples on a scatter_model-1 or -2 context: for each (emission
  * pixel, angle, u_bin, energy) the network inputs X_dev[n][8], the target
  * target_dev[n] and (nullable) the exact first-order scatter sum
  * scatter_dev[n] (Sec. 2.2), every path weight evaluated in FP64 from the
  * context's line integrals and scatter-point factors (no full path table is
  * needed; any u is accepted, the network is meant for the far field).
- * Errors: ENOTSUP for scatter_model 0, ERANGE for a pixel off the support or
+ * Errors: ENOTSUP for scatter_model 0, ERANGE for a pixel off the emission set or
  * an invalid angle, position or energy. */
 lmosem_status lmosem_surrogate_samples(lmosem_ctx *ctx, const int32_t *pixel, const int32_t *angle,
                                        const float *u_bin, const float *energy, int64_t n, float *X_dev,

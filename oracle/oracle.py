@@ -28,6 +28,7 @@ _lib = None
 
 __all__ = ["build", "OracleModel", "os_lm_mlem", "subset_update", "log_likelihood",
            "surrogate_features", "surrogate_target", "line_extent", "binned_rows", "binned_os_mlem",
+           "emission_mask",
            "compton_energy", "kn_shape", "kn_total", "rho", "psi_bar", "resp_K", "resp_D",
            "resp_G", "resp_W", "line_integral", "circle_mean", "default_threads"]
 
@@ -381,6 +382,28 @@ def binned_os_mlem(H: np.ndarray, y: np.ndarray, row_angle: np.ndarray, n_subset
             b = Hi.T @ ratio
             f = np.where(sens > 0, f * b / np.where(sens > 0, sens, 1.0), f)
     return f
+
+
+def emission_mask(image: np.ndarray, mu: np.ndarray, rel_threshold: float, margin_px: int) -> np.ndarray:
+    """Emission set from a crude image (Sec. 2.2: the estimate is confined to
+    a rough object boundary from a binned OS-MLEM, since the work per
+    iteration grows with the number of estimated pixels).  Reading: the
+    boundary is {image >= rel_threshold * max(image)} grown by every pixel
+    offset (di, dj) with di^2 + dj^2 <= margin_px^2, then intersected with
+    mu > 0; the threshold comparison is in float64.  Returns a float32 0/1
+    map."""
+    img = np.asarray(image, np.float64)
+    ny, nx = img.shape
+    hot = img >= rel_threshold * img.max()
+    m = int(margin_px)
+    padded = np.zeros((ny + 2 * m, nx + 2 * m), bool)
+    padded[m:m + ny, m:m + nx] = hot
+    grown = np.zeros((ny, nx), bool)
+    for dj in range(-m, m + 1):
+        for di in range(-m, m + 1):
+            if di * di + dj * dj <= m * m:
+                grown |= padded[m + dj:m + dj + ny, m + di:m + di + nx]
+    return (grown & (np.asarray(mu) > 0)).astype(np.float32)
 
 
 def os_lm_mlem(H: np.ndarray, angle: np.ndarray, sens_subsets: np.ndarray, n_iters: int,

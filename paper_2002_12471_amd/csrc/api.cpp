@@ -394,6 +394,11 @@ uint32_t lmosem_abi_version(void) { return LMOSEM_ABI_VERSION; }
 const char *lmosem_last_error(const lmosem_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void *hip_stream, lmosem_ctx **out) {
+    return lmosem_create_emission(cfg, mu_dev, nullptr, hip_stream, out);
+}
+
+lmosem_status lmosem_create_emission(const lmosem_config *cfg, const float *mu_dev, const float *emission_dev,
+                                     void *hip_stream, lmosem_ctx **out) {
     if (!cfg || !mu_dev || !out) return LMOSEM_EINVAL;
     *out = nullptr;
     std::string why;
@@ -405,19 +410,31 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     const int n_pix = cfg->nx * cfg->ny;
     std::vector<float> mu(n_pix);
     hipError_t e = hipMemcpyAsync(mu.data(), mu_dev, sizeof(float) * n_pix, hipMemcpyDeviceToHost, c->st);
+    std::vector<float> em;
+    if (e == hipSuccess && emission_dev) {
+        em.resize(n_pix);
+        e = hipMemcpyAsync(em.data(), emission_dev, sizeof(float) * n_pix, hipMemcpyDeviceToHost, c->st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) { delete c; return LMOSEM_EDEVICE; }
+    // the support (mu > 0) with the emission pixels first
     std::vector<int> p_pix, q_of_pix(n_pix, -1);
-    for (int p = 0; p < n_pix; ++p) {
+    for (int p = 0; p < n_pix; ++p)
         if (!(mu[p] >= 0.0f) || !std::isfinite(mu[p])) { delete c; return LMOSEM_ERANGE; }
-        if (mu[p] > 0.0f) { q_of_pix[p] = (int)p_pix.size(); p_pix.push_back(p); }
-    }
-    if (p_pix.empty()) { delete c; return LMOSEM_ERANGE; }
+    for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < n_pix; ++p) {
+            const bool emits = em.empty() || em[p] > 0.0f;
+            if (mu[p] > 0.0f && emits == (pass == 0)) { q_of_pix[p] = (int)p_pix.size(); p_pix.push_back(p); }
+        }
+    int n_q = 0;
+    for (int p = 0; p < n_pix; ++p) n_q += mu[p] > 0.0f && (em.empty() || em[p] > 0.0f);
+    if (n_q == 0) { delete c; return LMOSEM_ERANGE; }
 
     Geo &g = c->g;
     g.nx = cfg->nx; g.ny = cfg->ny; g.n_pix = n_pix;
     g.n_p = (int)p_pix.size();
-    g.n_qpad = (g.n_p + 63) / 64 * 64;
+    g.n_q = n_q;
+    g.n_qpad = (g.n_q + 63) / 64 * 64;
     g.n_rpad = g.n_p + kRankPad;
     g.n_angles = cfg->n_angles; g.n_bins = cfg->n_bins; g.n_subsets = cfg->n_subsets;
     g.scatter = cfg->scatter_model != 0;
@@ -441,7 +458,9 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
         cs[2 * a] = cos(th);
         cs[2 * a + 1] = sin(th);
     }
-#define CK(call, what) do { e = (call); if (e != hipSuccess) { lmosem_destroy(c); return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE; } } while (0)
+// an allocation failure also clears HIP's last-error state, so that later
+// calls of the caller's runtime do not report it again
+#define CK(call, what) do { e = (call); if (e != hipSuccess) { lmosem_destroy(c); if (e == hipErrorOutOfMemory) (void)hipGetLastError(); return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE; } } while (0)
     CK(hipMalloc(&c->t.p_pix, sizeof(int) * (g.n_p + n_pix)), "alloc");
     CK(hipMalloc(&c->t.mu, sizeof(float) * n_pix), "alloc");
     CK(hipMalloc(&c->t.cs, sizeof(double) * 2 * g.n_angles), "alloc");
@@ -458,6 +477,7 @@ lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void 
     e = build_tables(g, c->t, !c->surrogate, c->surrogate, c->st, err, c->table_bytes);
     if (e != hipSuccess) {
         lmosem_destroy(c);
+        if (e == hipErrorOutOfMemory) (void)hipGetLastError();
         return e == hipErrorOutOfMemory ? LMOSEM_ENOMEM : LMOSEM_EDEVICE;
     }
     c->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -677,7 +697,7 @@ lmosem_status lmosem_surrogate_samples(lmosem_ctx *c, const int32_t *pixel, cons
     if (n < 0 || (n > 0 && (!pixel || !angle || !u_bin || !energy || !X_dev || !target_dev)))
         return set_err(c, LMOSEM_EINVAL, "bad sample arrays");
     // the samples' angles, positions and energies follow the event rules;
-    // their pixels must lie on the support
+    // their pixels must lie in the emission set
     lmosem_events ev{n, angle, u_bin, energy};
     lmosem_status st = LMOSEM_OK;
     if (!check_events(c, &ev, st)) return st;
@@ -690,8 +710,8 @@ lmosem_status lmosem_surrogate_samples(lmosem_ctx *c, const int32_t *pixel, cons
         e = hipMemcpy(qop.data(), c->t.p_pix + c->g.n_p, sizeof(int) * c->g.n_pix, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return dev_err(c, "samples", e);
         for (int32_t p : px)
-            if (p < 0 || p >= c->g.n_pix || qop[p] < 0)
-                return set_err(c, LMOSEM_ERANGE, "sample pixel outside the support");
+            if (p < 0 || p >= c->g.n_pix || qop[p] < 0 || qop[p] >= c->g.n_q)
+                return set_err(c, LMOSEM_ERANGE, "sample pixel outside the emission set");
     }
     hipError_t e = surrogate_samples(c->g, c->t, pixel, angle, u_bin, energy, n, X_dev, target_dev, scatter_dev,
                                      c->st);
@@ -744,6 +764,24 @@ lmosem_status lmosem_bin_events(lmosem_ctx *c, const lmosem_events *ev, int32_t 
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     hipFree(edges);
     return e == hipSuccess ? LMOSEM_OK : dev_err(c, "bin events", e);
+}
+
+lmosem_status lmosem_emission_mask(lmosem_ctx *c, const float *image_dev, double rel_threshold, int32_t margin_px,
+                                   float *mask_dev) {
+    GUARD(c);
+    if (!image_dev || !mask_dev || !(rel_threshold >= 0.0 && rel_threshold <= 1.0) || margin_px < 0 || margin_px > 32)
+        return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    float *mx = nullptr, host[2] = {0.0f, 0.0f};
+    hipError_t e = hipMalloc(&mx, 2 * sizeof(float));
+    if (e == hipSuccess) e = launch_image_max(image_dev, c->g.n_pix, mx, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, mx, sizeof host, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(mx);
+    if (e != hipSuccess) return dev_err(c, "emission mask", e);
+    if (host[1] != 0.0f) return set_err(c, LMOSEM_ERANGE, "image values must be finite and >= 0");
+    e = launch_emission_mask(c->g, c->t.mu, image_dev, rel_threshold * (double)host[0], margin_px, mask_dev, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    return e == hipSuccess ? LMOSEM_OK : dev_err(c, "emission mask", e);
 }
 
 lmosem_status lmosem_binned_rows(lmosem_ctx *c, int32_t n_pos, const double *e_edges, int32_t n_ebins, int64_t n,
@@ -898,7 +936,8 @@ std::string tune_key(const lmosem_ctx *c, const lmosem_evset *s) {
     int lg = 0;
     while ((1 << (lg + 1)) <= std::max(1, s->s.max_rows)) ++lg;
     char buf[160];
-    snprintf(buf, sizeof buf, "np=%d na=%d ns=%d real=%d rows2^%d", c->g.n_p, c->g.n_angles, c->g.n_subsets,
+    snprintf(buf, sizeof buf, "np=%d nq=%d na=%d ns=%d real=%d rows2^%d", c->g.n_p, c->g.n_q, c->g.n_angles,
+             c->g.n_subsets,
              s->s.n_real, lg);
     return buf;
 }
@@ -1040,13 +1079,14 @@ lmosem_status lmosem_get_stats(const lmosem_ctx *c, lmosem_stats *out) {
     if (e == hipSuccess) e = drain_timing(const_cast<lmosem_ctx *>(c));
     if (e != hipSuccess) return LMOSEM_EDEVICE;
     out->n_support = c->g.n_p;
+    out->n_emission = c->g.n_q;
     out->skipped_events = (int64_t)sk;
     out->inner_terms = c->terms;
     out->useful_terms = c->useful;
     out->table_ms = c->table_ms;
     out->table_bytes = c->table_bytes;
     out->event_tile = c->ev_tile;
-    out->reserved = 0;
+
     out->forward_launches = c->launches[0];
     out->forward_ms = c->ms[0];
     out->backproject_launches = c->launches[1];

@@ -34,7 +34,7 @@ __device__ inline double energy_mass(const Geo &g, double ep, double e0, double 
 }
 
 // H[row][q] for the bins listed in row_bin (flat id (a * n_pos + b) * n_e + k);
-// one block row per bin, one thread per support pixel; padding columns are 0.
+// one block row per bin, one thread per emission pixel; padding columns are 0.
 __global__ __launch_bounds__(256) void k_binned_rows(Geo g, const int *__restrict__ p_pix,
                                                      const double *__restrict__ cs, const double *__restrict__ Ld,
                                                      const double *__restrict__ Bt, const int *__restrict__ s_sorted,
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_binned_rows(Geo g, const int *__restric
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= g.n_qpad) return;
     float *out = H + (size_t)row * g.n_qpad + q;
-    if (q >= g.n_p) { *out = 0.0f; return; }
+    if (q >= g.n_q) { *out = 0.0f; return; }
     const int bin = row_bin[row];
     const int a = bin / (n_pos * n_e), b = (bin / n_e) % n_pos, k = bin % n_e;
     const double width = 2.0 * g.half_len / n_pos;

@@ -118,8 +118,8 @@ __global__ void k_tile_ranks(Geo g, Tile *__restrict__ tiles, int n_tiles,
         double u = ((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm;
         use += first_at_least(u + reach) - first_above(u - reach);
     }
-    terms[t] = (long long)(tl.r1 - tl.r0) * tl.n * g.n_p;
-    useful[t] = use * g.n_p;
+    terms[t] = (long long)(tl.r1 - tl.r0) * tl.n * g.n_q;
+    useful[t] = use * g.n_q;
 }
 
 hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,

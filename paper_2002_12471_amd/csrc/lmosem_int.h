@@ -18,8 +18,10 @@ constexpr int kRankPad = 8;              // padding rank rows per angle (never c
 // Geometry and physics constants shared by the kernels (host-computed, FP64).
 struct Geo {
     int nx, ny, n_pix;
-    int n_p;          // support pixels (emission = scatter = path-end set)
-    int n_qpad;       // n_p rounded up to a multiple of 64 (row stride of tables)
+    int n_p;          // support pixels (mu > 0): the path ends and scatter points
+    int n_q;          // emission pixels: support indices 0 .. n_q-1 (the support is
+                      // ordered with the emission pixels first)
+    int n_qpad;       // n_q rounded up to a multiple of 64 (row stride of H and the table)
     int n_rpad;       // rank rows per angle in the path table: n_p + kRankPad
     int n_angles, n_bins, n_subsets, scatter;
     double dx, bin_cm, half_len;
@@ -93,6 +95,9 @@ hipError_t plan_tiles(const Geo &g, const Tables &t, EvSet &set, int ev_tile, in
 // ---- binned data (binned.hip) ----
 hipError_t launch_binned_rows(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,
                               const int *row_bin_dev, int n_rows, float *H, hipStream_t st);
+hipError_t launch_image_max(const float *img, int n, float *out, hipStream_t st);
+hipError_t launch_emission_mask(const Geo &g, const float *mu, const float *img, double thr, int margin, float *mask,
+                                hipStream_t st);
 hipError_t launch_bin_events(const Geo &g, const lmosem_events &ev, int n_pos, const double *edges_dev, int n_e,
                              float *counts, hipStream_t st);
 hipError_t launch_gather_counts(const float *counts, const int *row_bin, int n_rows, float *y, hipStream_t st);

@@ -149,7 +149,7 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         for (int e = 0; e < EV; ++e)
             if (e < tl.n) Hq[(size_t)e * g.n_qpad] = acc[e];
     }
-    const float fq = (wave_on && q < g.n_p) ? f[(size_t)tl.real * g.n_qpad + q] : 0.0f;
+    const float fq = (wave_on && q < g.n_q) ? f[(size_t)tl.real * g.n_qpad + q] : 0.0f;
 #pragma unroll
     for (int e = 0; e < EV; ++e) {
         const float v = wave_sum(fq * acc[e]);
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ c
     const int q = blockIdx.x * 64 + lane;
     const int r = blockIdx.y;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    if (q < g.n_p) {
+    if (q < g.n_q) {
         const int c0 = crange[r], c1 = crange[r + 1];
         int c = c0 + wv;
         for (; c + 12 < c1; c += 16) {
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ c
     }
     part[wv][lane] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    if (wv == 0 && q < g.n_p) {
+    if (wv == 0 && q < g.n_q) {
         const float b = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
         const float s = sens[q];
         float *fp = f + (size_t)r * g.n_qpad + q;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ c
 
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
                          const float *sens, float *f, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3((g.n_p + 63) / 64, n_real), dim3(256), 0, st, g, crange, pb, sens, f);
+    hipLaunchKernelGGL(k_update, dim3((g.n_q + 63) / 64, n_real), dim3(256), 0, st, g, crange, pb, sens, f);
     return hipGetLastError();
 }
 
@@ -373,7 +373,7 @@ __global__ void k_sum_real(Geo g, const int *__restrict__ crange, const float *_
     if (q >= g.n_qpad) return;
     float b = 0.0f;
     for (int c = crange[r]; c < crange[r + 1]; ++c) b += pb[(size_t)c * g.n_qpad + q];
-    out[(size_t)r * g.n_qpad + q] = q < g.n_p ? b : 0.0f;
+    out[(size_t)r * g.n_qpad + q] = q < g.n_q ? b : 0.0f;
 }
 
 hipError_t launch_sum_real(const Geo &g, const int *crange, int n_real, const float *pb, float *out,
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_loglik(Geo g, const int *__restrict__ r
         const float m = mean[j];
         if (m > 1e-30f) s += log((double)m);
     }
-    for (int q = tid; q < g.n_p; q += 256) s -= (double)f[(size_t)r * g.n_qpad + q] * (double)sens[q];
+    for (int q = tid; q < g.n_q; q += 256) s -= (double)f[(size_t)r * g.n_qpad + q] * (double)sens[q];
     red[tid] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -419,7 +419,7 @@ __global__ void k_gather_image(Geo g, const int *__restrict__ p_pix, const float
     const int r = blockIdx.y;
     if (q >= g.n_qpad) return;
     float v = 0.0f;
-    if (q < g.n_p) v = img ? img[(size_t)r * stride + p_pix[q]] : 1.0f;
+    if (q < g.n_q) v = img ? img[(size_t)r * stride + p_pix[q]] : 1.0f;
     f[(size_t)r * g.n_qpad + q] = v;
 }
 
@@ -430,14 +430,14 @@ hipError_t launch_gather_image(const Geo &g, const Tables &t, const float *img, 
     return hipGetLastError();
 }
 
-// images [r][ny][nx] from compact f (0 off the support)
+// images [r][ny][nx] from compact f (0 off the emission set)
 __global__ void k_scatter_image(Geo g, const int *__restrict__ q_of_pix, const float *__restrict__ f,
                                 float *__restrict__ img) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (p >= g.n_pix) return;
     const int q = q_of_pix[p];
-    img[(size_t)r * g.n_pix + p] = q >= 0 ? f[(size_t)r * g.n_qpad + q] : 0.0f;
+    img[(size_t)r * g.n_pix + p] = (q >= 0 && q < g.n_q) ? f[(size_t)r * g.n_qpad + q] : 0.0f;
 }
 
 // q_of_pix is stored right after p_pix in the same allocation
@@ -499,7 +499,7 @@ __global__ void k_check_image(Geo g, const int *__restrict__ p_pix, const float 
                               int *__restrict__ bad) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     int b = 0;
-    if (q < g.n_p) {
+    if (q < g.n_q) {
         const float v = img[p_pix[q]];
         b = !(v >= 0.0f && v <= 3.4e38f);
     }
@@ -508,7 +508,7 @@ __global__ void k_check_image(Geo g, const int *__restrict__ p_pix, const float 
 }
 
 hipError_t launch_check_image(const Geo &g, const Tables &t, const float *img, int *bad, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_image, dim3((g.n_p + 255) / 256), dim3(256), 0, st, g, t.p_pix, img, bad);
+    hipLaunchKernelGGL(k_check_image, dim3((g.n_q + 255) / 256), dim3(256), 0, st, g, t.p_pix, img, bad);
     return hipGetLastError();
 }
 

@@ -205,8 +205,8 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ ba
                              const int2 *__restrict__ rr, int row_base, int j0, int rows, float *__restrict__ H,
                              uint8_t *__restrict__ near, float *__restrict__ X) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch < 2^31
-    if (k >= rows * g.n_p) return;
-    const int jr = j0 + k / g.n_p, q = k % g.n_p;
+    if (k >= rows * g.n_q) return;
+    const int jr = j0 + k / g.n_q, q = k % g.n_q;
     const int j = row_base + jr;   // index into the sorted events
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
@@ -246,8 +246,8 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ ba
 __global__ void k_surr_add(Geo g, int j0, int rows, const uint8_t *__restrict__ near, const float *__restrict__ y,
                            float *__restrict__ H) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= rows * g.n_p || near[k]) return;
-    const int jr = j0 + k / g.n_p, q = k % g.n_p;
+    if (k >= rows * g.n_q || near[k]) return;
+    const int jr = j0 + k / g.n_q, q = k % g.n_q;
     const float s0 = (float)(1.0 / (g.dx * g.sig_e));
     H[(size_t)jr * g.n_qpad + q] += s0 * fmaxf(__expf(y[k]) - kTargetFloor, 0.0f);
 }
@@ -261,7 +261,7 @@ __global__ void k_row_mean(Geo g, const int *__restrict__ rrange, int n_real, in
     while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (rrange[m] <= j) lo = m; else hi = m; }
     const float *fr = f + (size_t)lo * g.n_qpad;
     float s = 0.0f;
-    for (int q = threadIdx.x; q < g.n_p; q += 64) s = fmaf(fr[q], H[(size_t)j * g.n_qpad + q], s);
+    for (int q = threadIdx.x; q < g.n_q; q += 64) s = fmaf(fr[q], H[(size_t)j * g.n_qpad + q], s);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (threadIdx.x == 0) pmean[j] = s;
@@ -291,10 +291,10 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
     hipLaunchKernelGGL(k_event_column, dim3((rows + 63) / 64), dim3(64), 0, st, g, s, ev_angle + row_base,
                        su + row_base, rows, col4, rr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int rows_per = (int)std::max<int64_t>(1, pair_cap / g.n_p);
+    const int rows_per = (int)std::max<int64_t>(1, pair_cap / g.n_q);
     for (int j0 = 0; j0 < rows; j0 += rows_per) {
         const int nr = std::min(rows_per, rows - j0);
-        const int64_t pairs = (int64_t)nr * g.n_p;
+        const int64_t pairs = (int64_t)nr * g.n_q;
         hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, t.band,
                            t.band_w, t.band_lo, ev_angle, su, se, efac, col4, rr, row_base, j0, nr, H, near, X);
         if ((e = hipGetLastError()) != hipSuccess) return e;

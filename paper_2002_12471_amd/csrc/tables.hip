@@ -76,14 +76,15 @@ __global__ void k_line_away(Geo g, const float *__restrict__ mu, const int *__re
 }
 
 // Bt[s][q] = B(q, s) = mu(s) dx^2 exp(-l(q,s)) / (2 pi r): the probability that
-// a photon emitted at q interacts at the scatter point s (0 for s == q).
+// a photon emitted at q interacts at the scatter point s (0 for s == q, and
+// for a support pixel q outside the emission set, which emits nothing).
 __global__ void k_scatter_points(Geo g, const float *__restrict__ mu, const int *__restrict__ p_pix,
                                  double *__restrict__ Bt) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int s = blockIdx.y;
     if (q >= g.n_p) return;
     double b = 0.0;
-    if (q != s) {
+    if (q != s && q < g.n_q) {
         int pq = p_pix[q], ps = p_pix[s];
         int di = ps % g.nx - pq % g.nx, dj = ps / g.nx - pq / g.nx;
         double r = g.dx * sqrt((double)(di * di + dj * dj));
@@ -149,7 +150,7 @@ __global__ void k_path_table(Geo g, const int *__restrict__ p_pix, const double 
     float2 *Ta = T ? T + (size_t)a * g.n_rpad * g.n_qpad + q : nullptr;
     if (Ta)
         for (int r = g.n_p; r < g.n_rpad; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
-    if (q >= g.n_p) {
+    if (q >= g.n_q) {
         if (Ta)
             for (int r = 0; r < g.n_p; ++r) Ta[(size_t)r * g.n_qpad] = make_float2(kNegHuge, 0.0f);
         sens_a[(size_t)a * g.n_qpad + q] = 0.0;
@@ -183,7 +184,7 @@ __global__ void k_band_range(Geo g, const int *__restrict__ p_pix, const double 
                              int *__restrict__ band_len) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int a = blockIdx.y;
-    if (q >= g.n_p) return;
+    if (q >= g.n_q) return;
     const int pix = p_pix[q];
     const double uq = centre_x(g, pix) * -cs[2 * a + 1] + centre_y(g, pix) * cs[2 * a];
     const double reach = 6.0 * g.sig_u;
@@ -206,8 +207,8 @@ __global__ void k_band_table(Geo g, int band_w, const int *__restrict__ p_pix, c
     const int a = blockIdx.y;
     if (q >= g.n_qpad) return;
     float2 *out = band + (size_t)a * band_w * g.n_qpad + q;
-    const int lo = q < g.n_p ? band_lo[(size_t)a * g.n_p + q] : 0;
-    const int len = q < g.n_p ? band_len[(size_t)a * g.n_p + q] : 0;
+    const int lo = q < g.n_q ? band_lo[(size_t)a * g.n_p + q] : 0;
+    const int len = q < g.n_q ? band_len[(size_t)a * g.n_p + q] : 0;
     const double nx = cs[2 * a], ny = cs[2 * a + 1];
     const double log2_gnorm = -log2(sqrt(2.0 * M_PI) * g.sig_e);
     for (int k = 0; k < band_w; ++k) {
@@ -287,13 +288,16 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
     if (store_band && g.scatter) {
         CK(hipMalloc(&t.band_lo, sizeof(int) * g.n_angles * g.n_p), "alloc band ranges");
         CK(hipMalloc(&band_len, sizeof(int) * g.n_angles * g.n_p), "alloc band ranges");
-        hipLaunchKernelGGL(k_band_range, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix, t.cs,
+        hipLaunchKernelGGL(k_band_range, dim3((g.n_q + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix, t.cs,
                            t.us_sorted, t.band_lo, band_len);
         CK(hipGetLastError(), "band ranges");
         std::vector<int> len((size_t)g.n_angles * g.n_p);
         CK(hipMemcpyAsync(len.data(), band_len, sizeof(int) * len.size(), hipMemcpyDeviceToHost, st), "band ranges");
         CK(hipStreamSynchronize(st), "band ranges");
-        t.band_w = std::max(1, *std::max_element(len.begin(), len.end()));
+        // bands exist for the emission pixels only (q < n_q of every angle)
+        t.band_w = 1;
+        for (int a = 0; a < g.n_angles; ++a)
+            for (int q = 0; q < g.n_q; ++q) t.band_w = std::max(t.band_w, len[(size_t)a * g.n_p + q]);
         const size_t nb = (size_t)g.n_angles * t.band_w * g.n_qpad;
         CK(hipMalloc(&t.band, sizeof(float2) * nb), "alloc near-field table");
         hipLaunchKernelGGL(k_band_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g, t.band_w,

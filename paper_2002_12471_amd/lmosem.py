@@ -57,7 +57,7 @@ class lmosem_stats(ctypes.Structure):
     _fields_ = [("n_support", ctypes.c_int64), ("skipped_events", ctypes.c_int64),
                 ("inner_terms", ctypes.c_int64), ("useful_terms", ctypes.c_int64),
                 ("table_ms", ctypes.c_double), ("table_bytes", ctypes.c_int64),
-                ("event_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("event_tile", ctypes.c_int32), ("n_emission", ctypes.c_int32),
                 ("forward_launches", ctypes.c_int64), ("forward_ms", ctypes.c_double),
                 ("backproject_launches", ctypes.c_int64), ("backproject_ms", ctypes.c_double),
                 ("update_launches", ctypes.c_int64), ("update_ms", ctypes.c_double)]
@@ -68,6 +68,7 @@ _S = ctypes.c_int
 _sigs = {
     "lmosem_abi_version": (ctypes.c_uint32, []),
     "lmosem_create": (_S, [ctypes.POINTER(lmosem_config), _P, _P, ctypes.POINTER(_P)]),
+    "lmosem_create_emission": (_S, [ctypes.POINTER(lmosem_config), _P, _P, _P, ctypes.POINTER(_P)]),
     "lmosem_destroy": (None, [_P]),
     "lmosem_last_error": (ctypes.c_char_p, [_P]),
     "lmosem_sensitivity": (_S, [_P, ctypes.c_int32, _P]),
@@ -88,6 +89,7 @@ _sigs = {
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
     "lmosem_cache_rows": (_S, [_P, _P, ctypes.c_int32]),
     "lmosem_bin_events": (_S, [_P, ctypes.POINTER(lmosem_events), ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    "lmosem_emission_mask": (_S, [_P, _P, ctypes.c_double, ctypes.c_int32, _P]),
     "lmosem_binned_rows": (_S, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int64, _P, _P]),
     "lmosem_binned_reconstruct": (_S, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "lmosem_net_create": (_S, [_P, _P, ctypes.POINTER(_P)]),
@@ -162,6 +164,23 @@ def lmosem_create(geom: dict, mu: torch.Tensor, stream: torch.cuda.Stream | None
                            ctypes.byref(out))
     if s != OK:
         raise LmosemError(s, "lmosem_create rejected the configuration or the map")
+    return out
+
+
+def lmosem_create_emission(geom: dict, mu: torch.Tensor, emission: torch.Tensor | None,
+                           stream: torch.cuda.Stream | None = None):
+    """Context whose estimated image is restricted to {mu > 0, emission > 0};
+    emission is [ny][nx] float32 on the GPU, or None for the mu > 0 support."""
+    cfg = config(geom)
+    st = (stream or torch.cuda.current_stream(mu.device)).cuda_stream
+    if emission is not None and emission.numel() != mu.numel():
+        raise ValueError("emission and mu differ in size")
+    em = _dev_ptr(emission, torch.float32, "emission")
+    out = ctypes.c_void_p()
+    s = _lib.lmosem_create_emission(ctypes.byref(cfg), _dev_ptr(mu, torch.float32, "mu"), em,
+                                    ctypes.c_void_p(st), ctypes.byref(out))
+    if s != OK:
+        raise LmosemError(s, "lmosem_create_emission rejected the configuration, the map or the emission set")
     return out
 
 
@@ -242,7 +261,7 @@ def lmosem_set_tuning(ctx, event_tile: int):
 def lmosem_get_stats(ctx) -> dict:
     s = lmosem_stats()
     _check(ctx, _lib.lmosem_get_stats(ctx, ctypes.byref(s)))
-    return {k: getattr(s, k) for k, _ in lmosem_stats._fields_ if k != "reserved"}
+    return {k: getattr(s, k) for k, _ in lmosem_stats._fields_}
 
 
 def lmosem_set_timing(ctx, enable: bool):
@@ -275,6 +294,15 @@ def lmosem_bin_events(ctx, events: dict, n_pos: int, e_edges, counts_out: torch.
     ed = _edges(e_edges)
     _check(ctx, _lib.lmosem_bin_events(ctx, ctypes.byref(ev), int(n_pos), ed.ctypes.data, len(ed) - 1,
                                        _dev_ptr(counts_out, torch.float32, "counts")))
+
+
+def lmosem_emission_mask(ctx, image: torch.Tensor, rel_threshold: float, margin_px: int, mask_out: torch.Tensor):
+    """mask_out [ny][nx] = 1 on mu > 0 pixels within margin_px of a pixel with
+    image >= rel_threshold * max(image), else 0."""
+    if image.numel() != mask_out.numel():
+        raise ValueError("image and mask differ in size")
+    _check(ctx, _lib.lmosem_emission_mask(ctx, _dev_ptr(image, torch.float32, "image"), float(rel_threshold),
+                                          int(margin_px), _dev_ptr(mask_out, torch.float32, "mask")))
 
 
 def lmosem_binned_rows(ctx, n_pos: int, e_edges, bins: torch.Tensor, rows_out: torch.Tensor):
@@ -390,10 +418,11 @@ def lmosem_set_surrogate(ctx, net):
 class Context:
     """Owning wrapper: a context plus convenience allocation of outputs."""
 
-    def __init__(self, geom: dict, mu: torch.Tensor, stream: torch.cuda.Stream | None = None):
+    def __init__(self, geom: dict, mu: torch.Tensor, stream: torch.cuda.Stream | None = None,
+                 emission: torch.Tensor | None = None):
         self.geom = dict(geom)
         self.device = mu.device
-        self.handle = lmosem_create(geom, mu, stream)
+        self.handle = lmosem_create_emission(geom, mu, emission, stream)
 
     def close(self):
         if self.handle:

@@ -1,0 +1,288 @@
+"""GPU tests of the emission set (Sec. 2.2: the estimate is confined to a
+crude object boundary, found by a quick binned OS-MLEM, so that each
+iteration touches fewer pixels).
+
+A context built with an emission mask estimates only {mu > 0, mask > 0};
+scatter points and path ends stay the whole mu > 0 support.  Checked against
+the FP64 oracle with its pixel list set to the emission pixels, against the
+full-support context started from an image that is zero off the set, and the
+boundary kernel against the oracle's definition.  Tolerances as in
+test_gpu_parity."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O  # noqa: E402
+import synth  # noqa: E402
+
+
+def _lib():
+    from paper_2002_12471_amd import lmosem as L
+    return L
+
+
+def _rel(g, o):
+    return np.abs(np.asarray(g, np.float64) - o) / np.abs(o)
+
+
+def _image_ok(got, ref):
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    tol = np.where(ref >= 1e-2 * ref.max(), 1e-3 * ref, 1e-5 * ref.max())
+    return np.all(err <= tol), float(np.max(err / np.maximum(np.abs(ref), 1e-300)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.workload("tiny")
+    g = dict(w.geom.as_dict(), n_subsets=4)
+    act, mu = synth.phantom(w)
+    ev = synth.workload_events(w)
+    return dict(w=w, g=g, act=act, mu=mu, ev=ev)
+
+
+def _masks(act, mu):
+    """The true activity support, its hot part only, and a seeded random
+    subset of the mu > 0 support."""
+    rng = np.random.default_rng(21)
+    return {"activity": (act > 0).astype(np.float32),
+            "hot": (act >= 2).astype(np.float32),
+            "random": ((rng.random(mu.shape) < 0.6) & (mu > 0)).astype(np.float32)}
+
+
+@pytest.mark.parametrize("which", ["activity", "hot", "random"])
+@pytest.mark.parametrize("scatter_model", [1, 0])
+def test_emission_context_matches_oracle(tiny, dev, which, scatter_model):
+    """Sensitivities, forward means and 10 iterations of OS-LM-MLEM (4 subsets)
+    of a masked context against the oracle restricted to the emission pixels."""
+    L = _lib()
+    g, act, mu, ev = dict(tiny["g"], scatter_model=scatter_model), tiny["act"], tiny["mu"], tiny["ev"]
+    mask = _masks(act, mu)[which]
+    m = O.OracleModel(g, mu)
+    q_em = np.flatnonzero((mask.ravel() > 0) & (mu.ravel() > 0)).astype(np.int32)
+    assert 0 < len(q_em) < len(m.support)
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev), emission=torch.as_tensor(mask, device=dev))
+    try:
+        st = ctx.stats()
+        assert st["n_emission"] == len(q_em) and st["n_support"] == len(m.support)
+        sens = np.stack([ctx.sensitivity(i).cpu().numpy().ravel() for i in range(4)])
+        evd = _lib().events_to_device(ev, dev)
+        mean = ctx.forward(evd, torch.as_tensor(act, device=dev)).cpu().numpy()
+        img, ll = ctx.reconstruct(evd, 10, want_loglik=True)
+        img = img.cpu().numpy().ravel()
+    finally:
+        ctx.close()
+    off = np.setdiff1d(np.arange(mu.size), q_em)
+    assert np.all(sens[:, off] == 0) and np.all(img[off] == 0)
+    sens_ref = np.stack([m.sensitivity(i, qlist=q_em) for i in range(4)])
+    assert np.max(_rel(sens[:, q_em], sens_ref)) <= 2e-6
+    H = m.system_matrix(ev, qlist=q_em)
+    mean_ref = H @ act.ravel()[q_em].astype(np.float64)
+    live = mean_ref > 0
+    assert np.max(_rel(mean[live], mean_ref[live])) <= 1e-4 and np.all(mean[~live] == 0)
+    f_ref, ll_ref = O.os_lm_mlem(H, ev["angle"], sens_ref, 10, np.ones(len(q_em)), 4)
+    ok, worst = _image_ok(img[q_em], f_ref)
+    assert ok, worst
+    np.testing.assert_allclose(ll[0], ll_ref, rtol=1e-5)
+
+
+def _run_set(L, ctx, evd, start, n_iters, offsets=None, cache=False, tune=False):
+    evs = L.lmosem_events_load(ctx.handle, evd, offsets)
+    try:
+        if tune:
+            L.lmosem_autotune(ctx.handle, evs)
+        if cache:
+            L.lmosem_cache_rows(ctx.handle, evs, True)
+        img = torch.as_tensor(start, device=evd["angle"].device).contiguous()
+        L.lmosem_iterate(ctx.handle, evs, n_iters, img, n_real=1 if offsets is None else len(offsets) - 1)
+        torch.cuda.synchronize()
+        return img.cpu().numpy()
+    finally:
+        L.lmosem_events_free(evs)
+
+
+@pytest.mark.parametrize("cache", [False, True])
+def test_brain64_masked_equals_full_support_from_zero_start(dev, cache):
+    """brain64 (200k events, 8 subsets, autotuned), 3 iterations: the masked
+    context started from ones equals the full-support context started from an
+    image that is zero off the emission set (the mask is the activity support
+    grown by one pixel)."""
+    L = _lib()
+    w = synth.workload("brain64")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    ev = synth.workload_events(w)
+    evd = L.events_to_device(ev, dev)
+    X, Y = np.meshgrid(np.arange(mu.shape[1]), np.arange(mu.shape[0]))
+    hot = act > 0
+    grown = hot.copy()
+    for dj, di in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        grown |= np.roll(hot, (dj, di), axis=(0, 1))
+    mask = (grown & (mu > 0)).astype(np.float32)
+    full = L.Context(g, torch.as_tensor(mu, device=dev))
+    try:
+        ref = _run_set(L, full, evd, mask, 3, cache=cache, tune=True)[None]
+    finally:
+        full.close()
+    em = L.Context(g, torch.as_tensor(mu, device=dev), emission=torch.as_tensor(mask, device=dev))
+    try:
+        assert em.stats()["n_emission"] == int(mask.sum())
+        got = _run_set(L, em, evd, (mu > 0).astype(np.float32), 3, cache=cache, tune=True)[None]
+    finally:
+        em.close()
+    on = mask.ravel() > 0
+    r, gg = ref[0].ravel(), got[0].ravel()
+    assert np.all(r[~on] == 0) and np.all(gg[~on] == 0)
+    a, b = r[on].astype(np.float64), gg[on]
+    assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4
+
+
+def test_learned_scatter_masked_equals_full_support_from_zero_start(tiny, dev):
+    """The learned-scatter path (untrained network, two realisations): masked
+    against full support started from zero off the set."""
+    L = _lib()
+    g, act, mu = dict(tiny["g"], scatter_model=2), tiny["act"], tiny["mu"]
+    mask = _masks(act, mu)["activity"]
+    parts = [synth.workload_events(tiny["w"], realisation=r, n_events=n) for r, n in enumerate((2500, 1800))]
+    ev = {k: np.concatenate([p[k] for p in parts]) for k in ("angle", "u_bin", "energy")}
+    offsets = [0, 2500, 4300]
+    evd = L.events_to_device(ev, dev)
+    net = L.lmosem_net_create(synth.mlp_init_params(5))
+    out = []
+    try:
+        for emission, start in ((None, mask), (mask, (mu > 0).astype(np.float32))):
+            ctx = L.Context(g, torch.as_tensor(mu, device=dev),
+                            emission=None if emission is None else torch.as_tensor(emission, device=dev))
+            try:
+                L.lmosem_set_surrogate(ctx.handle, net)
+                out.append(_run_set(L, ctx, evd, np.stack([start, start]), 3, offsets=offsets))
+            finally:
+                ctx.close()
+    finally:
+        L.lmosem_net_destroy(net)
+    on = mask.ravel() > 0
+    for r in range(2):
+        a, b = out[0][r].ravel(), out[1][r].ravel()
+        assert np.all(a[~on] == 0) and np.all(b[~on] == 0)
+        a, b = a[on].astype(np.float64), b[on]
+        assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4, r
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_emission_mask_kernel_matches_oracle(tiny, dev, seed):
+    """The boundary kernel against the oracle's definition on seeded images
+    (sparse exponential values, exact ties at the threshold included)."""
+    L = _lib()
+    mu = tiny["mu"]
+    rng = np.random.default_rng(seed)
+    img = (rng.exponential(1.0, mu.shape) * (rng.random(mu.shape) < 0.2)).astype(np.float32)
+    img.flat[rng.integers(mu.size)] = 0.25 * img.max()   # a value exactly at t = 0.25
+    ctx = L.Context(tiny["g"], torch.as_tensor(mu, device=dev))
+    try:
+        img_d = torch.as_tensor(img, device=dev)
+        out = torch.empty_like(img_d)
+        for t in (0.0, 0.25, 0.6, 1.0):
+            for margin in (0, 1, 2, 5):
+                L.lmosem_emission_mask(ctx.handle, img_d, t, margin, out)
+                np.testing.assert_array_equal(out.cpu().numpy(), O.emission_mask(img, mu, t, margin))
+    finally:
+        ctx.close()
+
+
+def test_binned_boundary_then_list_mode(tiny, dev):
+    """The whole front end on the GPU: events binned (16 position bins, one
+    window), 3 binned OS-MLEM iterations, boundary at 5% with a 1-pixel
+    margin, then a masked context and 5 list-mode iterations.  Checked by
+    properties of the definitions: the mask holds every pixel at or above the
+    threshold, every mask pixel lies within the margin of one, and the
+    masked reconstruction matches the oracle on that emission set."""
+    L = _lib()
+    g, act, mu, ev = tiny["g"], tiny["act"], tiny["mu"], tiny["ev"]
+    edges = [g["win_lo_kev"], g["win_hi_kev"]]
+    ctx = L.Context(g, torch.as_tensor(mu, device=dev))
+    try:
+        evd = L.events_to_device(ev, dev)
+        counts = torch.empty(g["n_angles"] * 16, device=dev)
+        L.lmosem_bin_events(ctx.handle, evd, 16, edges, counts)
+        crude = torch.empty(mu.shape, device=dev)
+        L.lmosem_binned_reconstruct(ctx.handle, 16, edges, counts, 3, crude)
+        mask = torch.empty_like(crude)
+        L.lmosem_emission_mask(ctx.handle, crude, 0.05, 1, mask)
+        c, mk = crude.cpu().numpy().astype(np.float64), mask.cpu().numpy()
+    finally:
+        ctx.close()
+    hot = (c >= 0.05 * c.max()) & (mu > 0)
+    assert np.all(mk[hot] == 1) and np.all(mk[mu <= 0] == 0)
+    hj, hi = np.nonzero(hot)
+    for j, i in zip(*np.nonzero(mk)):
+        assert np.min((hj - j) ** 2 + (hi - i) ** 2) <= 1
+    q_em = np.flatnonzero(mk.ravel() > 0).astype(np.int32)
+    em = L.Context(g, torch.as_tensor(mu, device=dev), emission=mask)
+    try:
+        img = em.reconstruct(L.events_to_device(ev, dev), 5).cpu().numpy().ravel()
+    finally:
+        em.close()
+    m = O.OracleModel(g, mu)
+    sens = np.stack([m.sensitivity(i, qlist=q_em) for i in range(4)])
+    f_ref, _ = O.os_lm_mlem(m.system_matrix(ev, qlist=q_em), ev["angle"], sens, 5, np.ones(len(q_em)), 4)
+    ok, worst = _image_ok(img[q_em], f_ref)
+    assert ok, worst
+
+
+def test_emission_edge_cases(tiny, dev):
+    L = _lib()
+    g, act, mu = tiny["g"], tiny["act"], tiny["mu"]
+    mu_d = torch.as_tensor(mu, device=dev)
+    # no mask: the whole support emits
+    ctx = L.Context(g, mu_d, emission=None)
+    try:
+        st = ctx.stats()
+        assert st["n_emission"] == st["n_support"] == int((mu > 0).sum())
+        img = torch.as_tensor(np.full(mu.shape, np.nan, np.float32), device=dev)
+        with pytest.raises(L.LmosemError, match="ERANGE"):
+            L.lmosem_emission_mask(ctx.handle, img, 0.1, 1, torch.empty_like(img))
+        with pytest.raises(L.LmosemError, match="EINVAL"):
+            L.lmosem_emission_mask(ctx.handle, torch.zeros_like(img), 1.5, 1, torch.empty_like(img))
+        with pytest.raises(L.LmosemError, match="EINVAL"):
+            L.lmosem_emission_mask(ctx.handle, torch.zeros_like(img), 0.1, 33, torch.empty_like(img))
+        # an all-zero image: every value reaches a zero threshold, the mask is the support
+        out = torch.empty_like(img)
+        L.lmosem_emission_mask(ctx.handle, torch.zeros_like(img), 0.3, 0, out)
+        np.testing.assert_array_equal(out.cpu().numpy(), (mu > 0).astype(np.float32))
+    finally:
+        ctx.close()
+    # empty emission sets: a zero mask, and a mask only where mu == 0
+    for bad in (np.zeros_like(mu), (mu <= 0).astype(np.float32)):
+        with pytest.raises(L.LmosemError, match="ERANGE"):
+            L.Context(g, mu_d, emission=torch.as_tensor(bad, device=dev))
+    # a single emission pixel
+    one = np.zeros_like(mu)
+    one.flat[np.flatnonzero(act.ravel() > 0)[0]] = 1.0
+    ctx = L.Context(g, mu_d, emission=torch.as_tensor(one, device=dev))
+    try:
+        assert ctx.stats()["n_emission"] == 1
+        img = ctx.reconstruct(L.events_to_device(tiny["ev"], dev), 2).cpu().numpy()
+        assert np.count_nonzero(img) == 1 and img.flat[np.flatnonzero(one)[0]] > 0
+    finally:
+        ctx.close()
+    # surrogate samples only at emission pixels
+    mask = _masks(act, mu)["activity"]
+    ctx = L.Context(dict(g, scatter_model=2), mu_d, emission=torch.as_tensor(mask, device=dev))
+    try:
+        outside = int(np.flatnonzero((mu.ravel() > 0) & (mask.ravel() == 0))[0])
+        inside = int(np.flatnonzero(mask.ravel() > 0)[0])
+        args = [torch.tensor([0], dtype=torch.int32, device=dev), torch.tensor([8.0], device=dev),
+                torch.tensor([120.0], device=dev)]
+        L.lmosem_surrogate_samples(ctx.handle, torch.tensor([inside], dtype=torch.int32, device=dev), *args)
+        with pytest.raises(L.LmosemError, match="ERANGE"):
+            L.lmosem_surrogate_samples(ctx.handle, torch.tensor([outside], dtype=torch.int32, device=dev), *args)
+    finally:
+        ctx.close()
