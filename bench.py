@@ -528,6 +528,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.time()
     ctx = L.Context(g, mu_d, stream, emission=emission)
+    ctx.sensitivity(-1)   # the list-mode tables are built at their first use
     torch.cuda.synchronize()
     t_create = time.time() - t0
     if args.event_tile:

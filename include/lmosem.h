@@ -119,8 +119,9 @@ typedef struct {
     int64_t inner_terms;        /* (event, emission pixel, path end) terms evaluated by
                                    the forward projection, since create */
     int64_t useful_terms;       /* of those, terms with a non-zero position response */
-    double table_ms;            /* time of the table build in lmosem_create */
-    int64_t table_bytes;        /* device bytes held by the path tables */
+    double table_ms;            /* time of the table builds so far (lmosem_create, and
+                                   the path tables at the first list-mode call) */
+    int64_t table_bytes;        /* device bytes held by the tables built so far */
     int32_t event_tile;         /* events per forward-projection tile */
     int32_t n_emission;         /* emission pixels (the estimated image), <= n_support */
     /* kernel times from HIP events on the context's stream, recorded only
@@ -138,11 +139,14 @@ uint32_t lmosem_abi_version(void);
 
 /* Build a context for one attenuation map: validates the configuration and
  * mu (finite, >= 0, at least one pixel > 0; mu is read on the device and
- * copied once to the host), computes every path's weight and end energy
- * (attenuation line integrals, Klein-Nishina and Compton factors; the model
- * of s_eff in Eq. 4) and the per-subset sensitivity images (the
- * denominators of Eq. 6/7).  mu_dev: [ny][nx] float32 in 1/cm at e0_kev.
- * hip_stream: a hipStream_t, or NULL for the null stream.
+ * copied once to the host) and computes the attenuation line integrals, the
+ * scatter-point factors and the ranked path ends (the parts of the model of
+ * s_eff in Eq. 4 that every use needs).  The first call that needs them
+ * (sensitivity, forward, backprojection, updates, event sets) builds every
+ * path's weight and end energy and the per-subset sensitivity images (the
+ * denominators of Eq. 6/7); that call returns ENOMEM if they do not fit,
+ * and the binned functions never need them.  mu_dev: [ny][nx] float32 in
+ * 1/cm at e0_kev.  hip_stream: a hipStream_t, or NULL for the null stream.
  * Errors: EINVAL (config), ERANGE (mu), ENOMEM, EDEVICE. */
 lmosem_status lmosem_create(const lmosem_config *cfg, const float *mu_dev, void *hip_stream,
                             lmosem_ctx **out);

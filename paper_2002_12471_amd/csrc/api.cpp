@@ -29,6 +29,9 @@ struct lmosem_ctx {
     int64_t terms = 0, useful = 0;
     double table_ms = 0.0;
     int64_t table_bytes = 0;
+    // the path table (or near-field band), sensitivities and primary weights
+    // are built at the first call that needs them (binned work does not)
+    bool paths_ready = false;
     // HIP graphs: one captured iteration per prepared set, replayed on an
     // internal stream ordered after the caller's stream by events
     bool graphs = true;
@@ -385,6 +388,34 @@ lmosem_status iterate_set(lmosem_ctx *c, lmosem_evset *s, int n_iters, double *l
         if ((c)->poisoned) return LMOSEM_ESTATE;                              \
     } while (0)
 
+// build the list-mode tables on first use; a failed build frees what it
+// allocated and leaves the context usable (ENOMEM for a table too large)
+lmosem_status ensure_paths(lmosem_ctx *c) {
+    if (c->paths_ready) return LMOSEM_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string err;
+    int64_t bytes = 0;
+    const hipError_t e = build_paths(c->g, c->t, !c->surrogate, c->surrogate, c->st, err, bytes);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(c->st);
+        hipFree(c->t.T); hipFree(c->t.prim); hipFree(c->t.sens); hipFree(c->t.sens_all);
+        hipFree(c->t.band); hipFree(c->t.band_lo);
+        c->t.T = nullptr; c->t.prim = nullptr; c->t.sens = nullptr; c->t.sens_all = nullptr;
+        c->t.band = nullptr; c->t.band_lo = nullptr;
+        return alloc_err(c, ("path tables: " + err).c_str(), e);
+    }
+    c->table_bytes += bytes;
+    c->table_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->paths_ready = true;
+    return LMOSEM_OK;
+}
+
+#define PATHS(c)                                                              \
+    do {                                                                      \
+        const lmosem_status ps_ = ensure_paths(c);                            \
+        if (ps_ != LMOSEM_OK) return ps_;                                     \
+    } while (0)
+
 }  // namespace
 
 extern "C" {
@@ -474,7 +505,7 @@ lmosem_status lmosem_create_emission(const lmosem_config *cfg, const float *mu_d
     CK(hipMemcpyAsync(c->t.cs, cs.data(), sizeof(double) * 2 * g.n_angles, hipMemcpyHostToDevice, c->st), "upload");
 #undef CK
     std::string err;
-    e = build_tables(g, c->t, !c->surrogate, c->surrogate, c->st, err, c->table_bytes);
+    e = build_base(g, c->t, c->st, err, c->table_bytes);
     if (e != hipSuccess) {
         lmosem_destroy(c);
         if (e == hipErrorOutOfMemory) (void)hipGetLastError();
@@ -498,12 +529,14 @@ void lmosem_destroy(lmosem_ctx *c) {
     if (c->gst) hipStreamDestroy(c->gst);
     hipFree(c->t.p_pix); hipFree(c->t.mu); hipFree(c->t.cs); hipFree(c->t.s_sorted); hipFree(c->t.us_sorted); hipFree(c->t.mu_sorted);
     hipFree(c->t.T); hipFree(c->t.sens); hipFree(c->t.sens_all); hipFree(c->t.Ldet); hipFree(c->t.Lback);
-    hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->t.Ld); hipFree(c->t.Bt); hipFree(c->bad_dev); hipFree(c->skipped_dev);
+    hipFree(c->t.prim); hipFree(c->t.band); hipFree(c->t.band_lo); hipFree(c->t.Ld); hipFree(c->t.Bt);
+    hipFree(c->t.D_sorted); hipFree(c->bad_dev); hipFree(c->skipped_dev);
     delete c;
 }
 
 lmosem_status lmosem_sensitivity(lmosem_ctx *c, int32_t subset, float *sens_dev) {
     GUARD(c);
+    PATHS(c);
     if (!sens_dev || subset < -1 || subset >= c->g.n_subsets) return set_err(c, LMOSEM_EINVAL, "bad subset");
     const float *src = subset < 0 ? c->t.sens_all : c->t.sens + (size_t)subset * c->g.n_qpad;
     hipError_t e = launch_scatter_image(c->g, c->t, src, 1, sens_dev, c->st);
@@ -513,6 +546,7 @@ lmosem_status lmosem_sensitivity(lmosem_ctx *c, int32_t subset, float *sens_dev)
 lmosem_status lmosem_events_load(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch,
                                  lmosem_evset **out) {
     GUARD(c);
+    PATHS(c);
     if (!out) return set_err(c, LMOSEM_EINVAL, "null output");
     *out = nullptr;
     return load_set(c, ev, batch, -1, out);
@@ -523,6 +557,7 @@ void lmosem_events_free(lmosem_evset *s) { free_set(s); }
 lmosem_status lmosem_iterate(lmosem_ctx *c, lmosem_evset *s, int32_t n_iters, float *images_dev,
                              double *loglik_host) {
     GUARD(c);
+    PATHS(c);
     if (!s || s->s.ctx != c || !images_dev || n_iters < 0) return set_err(c, LMOSEM_EINVAL, "bad arguments");
     const Geo &g = c->g;
     hipError_t e = launch_gather_image(g, c->t, images_dev, s->s.n_real, g.n_pix, s->f, 0, c->st);
@@ -537,6 +572,7 @@ lmosem_status lmosem_reconstruct(lmosem_ctx *c, const lmosem_events *ev, const l
                                  int32_t n_iters, const float *init_dev, float *images_dev,
                                  double *loglik_host) {
     GUARD(c);
+    PATHS(c);
     if (!images_dev || n_iters < 0) return set_err(c, LMOSEM_EINVAL, "bad arguments");
     const Geo &g = c->g;
     hipError_t e;
@@ -567,6 +603,7 @@ lmosem_status lmosem_reconstruct(lmosem_ctx *c, const lmosem_events *ev, const l
 lmosem_status lmosem_subset_update(lmosem_ctx *c, int32_t subset, const lmosem_events *ev, float *image_dev,
                                    float *event_mean_dev) {
     GUARD(c);
+    PATHS(c);
     if (!image_dev || subset < 0 || subset >= c->g.n_subsets) return set_err(c, LMOSEM_EINVAL, "bad arguments");
     const char *val = getenv("LMOSEM_VALIDATE");
     if (val && atoi(val) == 1 && ev && ev->n > 0) {
@@ -596,6 +633,7 @@ lmosem_status lmosem_subset_update(lmosem_ctx *c, int32_t subset, const lmosem_e
 
 lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float *image_dev, float *mean_dev) {
     GUARD(c);
+    PATHS(c);
     if (!image_dev || !mean_dev) return set_err(c, LMOSEM_EINVAL, "bad arguments");
     lmosem_evset *s = nullptr;
     lmosem_status st = load_set(c, ev, nullptr, 0, &s);
@@ -616,6 +654,7 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
 lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const float *weights_dev,
                                  float *image_dev) {
     GUARD(c);
+    PATHS(c);
     if (!image_dev || (!weights_dev && ev && ev->n > 0)) return set_err(c, LMOSEM_EINVAL, "bad arguments");
     lmosem_evset *s = nullptr;
     lmosem_status st = load_set(c, ev, nullptr, 0, &s);
@@ -846,10 +885,12 @@ lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const doub
     }
     std::vector<int> rr;   // per subset {0, rows}
     for (int i = 0; i < g.n_subsets; ++i) { rr.push_back(0); rr.push_back(sub_off[i + 1] - sub_off[i]); }
+    std::vector<int> row0(g.n_angles);   // first row of each angle
+    for (int a = 0; a < g.n_angles; ++a) row0[a] = sub_off[a % g.n_subsets] + (a / g.n_subsets) * per_angle;
 
     float *H = nullptr, *y = nullptr, *mean = nullptr, *inv = nullptr, *w = nullptr, *ones = nullptr, *pb = nullptr;
     float *sens = nullptr, *f = nullptr;
-    int *d_rows = nullptr, *d_cr = nullptr, *d_rr = nullptr;
+    int *d_rows = nullptr, *d_cr = nullptr, *d_rr = nullptr, *d_row0 = nullptr;
     Chunk *d_chunks = nullptr;
     unsigned long long *dead = nullptr;
     hipError_t e = hipSuccess;
@@ -866,6 +907,7 @@ lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const doub
     al((void **)&d_rows, sizeof(int) * n_rows);
     al((void **)&d_cr, sizeof(int) * cr.size());
     al((void **)&d_rr, sizeof(int) * rr.size());
+    al((void **)&d_row0, sizeof(int) * row0.size());
     al((void **)&d_chunks, sizeof(Chunk) * std::max<size_t>(chunks.size(), 1));
     al((void **)&dead, sizeof(unsigned long long));
     auto up = [&](void *dst, const void *src, size_t bytes) {
@@ -874,9 +916,13 @@ lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const doub
     up(d_rows, row_bin.data(), sizeof(int) * n_rows);
     up(d_cr, cr.data(), sizeof(int) * cr.size());
     up(d_rr, rr.data(), sizeof(int) * rr.size());
+    up(d_row0, row0.data(), sizeof(int) * row0.size());
     up(d_chunks, chunks.data(), sizeof(Chunk) * chunks.size());
     if (e == hipSuccess) e = launch_fill(ones, max_rows, 1.0f, c->st);
-    if (e == hipSuccess) e = launch_binned_rows(g, c->t, n_pos, edges, n_ebins, d_rows, n_rows, H, c->st);
+    if (e == hipSuccess) {
+        e = launch_binned_rows_all(g, c->t, n_pos, edges, n_ebins, d_row0, H, c->st);
+        if (e == hipErrorNotSupported) e = launch_binned_rows(g, c->t, n_pos, edges, n_ebins, d_rows, n_rows, H, c->st);
+    }
     if (e == hipSuccess) e = launch_gather_counts(counts_dev, d_rows, n_rows, y, c->st);
     // the binned sensitivity of each subset: column sums of its rows
     for (int i = 0; i < g.n_subsets && e == hipSuccess; ++i) {
@@ -898,7 +944,7 @@ lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const doub
     if (e == hipSuccess) e = launch_scatter_image(g, c->t, f, 1, image_dev, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     for (void *p : {(void *)H, (void *)y, (void *)mean, (void *)inv, (void *)w, (void *)ones, (void *)pb, (void *)sens,
-                    (void *)f, (void *)d_rows, (void *)d_cr, (void *)d_rr, (void *)d_chunks, (void *)dead,
+                    (void *)f, (void *)d_rows, (void *)d_cr, (void *)d_rr, (void *)d_row0, (void *)d_chunks, (void *)dead,
                     (void *)edges})
         hipFree(p);
     if (e == hipErrorOutOfMemory) { (void)hipGetLastError(); return set_err(c, LMOSEM_ENOMEM, "binned reconstruction: out of memory"); }
@@ -907,6 +953,7 @@ lmosem_status lmosem_binned_reconstruct(lmosem_ctx *c, int32_t n_pos, const doub
 
 lmosem_status lmosem_cache_rows(lmosem_ctx *c, lmosem_evset *s, int32_t enable) {
     GUARD(c);
+    PATHS(c);
     if (!s || s->s.ctx != c) return set_err(c, LMOSEM_EINVAL, "bad event set");
     drop_graphs(s);
     s->rows_valid = false;
@@ -993,6 +1040,7 @@ extern "C" {
 lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_tile, int32_t *chunk_rows,
                               int32_t *use_graphs) {
     GUARD(c);
+    PATHS(c);
     if (!s || s->s.ctx != c) return set_err(c, LMOSEM_EINVAL, "bad event set");
     const Geo &g = c->g;
     EvSet &v = s->s;

@@ -66,6 +66,83 @@ __global__ __launch_bounds__(256) void k_binned_rows(Geo g, const int *__restric
     *out = (float)sum;
 }
 
+// All bins of every angle at once.  A path end's position response spans at
+// most W consecutive position bins, and path ends are ranked by position, so
+// one thread per (angle, emission pixel) walks the ranks once, evaluating each
+// path weight once (rather than once per bin that the path reaches), with W
+// bins of accumulators that slide along the detector.  The position-bin
+// masses depend on the rank only and come precomputed (k_rank_bin_masses).
+template <int W>
+__global__ void k_rank_bin_masses(Geo g, const double *__restrict__ us_sorted, int n_pos, int *__restrict__ rb0,
+                                  double *__restrict__ rpm) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, a = blockIdx.y;
+    if (r >= g.n_p) return;
+    const size_t o = (size_t)a * g.n_p + r;
+    const double us = us_sorted[o];
+    const double width = 2.0 * g.half_len / n_pos;
+    const int b0 = min(max((int)floor((us - 3.0 * g.sig_u + g.half_len) / width), 0), n_pos - 1);
+    rb0[o] = b0;
+    for (int i = 0; i < W; ++i) {
+        const int b = b0 + i;
+        const double u0 = -g.half_len + b * width, u1 = u0 + width;
+        rpm[o * W + i] = b < n_pos ? pos_mass(g, us, u0, u1) : 0.0;
+    }
+}
+
+template <int W, int KMAX>
+__global__ __launch_bounds__(64) void k_binned_rows_all(Geo g, const int *__restrict__ p_pix,
+                                                        const double *__restrict__ cs, const double *__restrict__ Ld,
+                                                        const double *__restrict__ Bt,
+                                                        const int *__restrict__ s_sorted, const int *__restrict__ rb0,
+                                                        const double *__restrict__ rpm, int n_pos,
+                                                        const double *__restrict__ edges, int n_e,
+                                                        const int *__restrict__ angle_row0, float *__restrict__ H) {
+    const int a = blockIdx.y;
+    const int q = blockIdx.x * 64 + threadIdx.x;   // n_qpad is a multiple of 64
+    const bool active = q < g.n_q;
+    const double nx = cs[2 * a], ny = cs[2 * a + 1];
+    const double s2 = M_SQRT2 * g.sig_e;
+    float *Hq = H + (size_t)angle_row0[a] * g.n_qpad + q;
+    double acc[W][KMAX];
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) acc[i][k] = 0.0;
+    int base = 0;
+    // write the lowest bin of the window and slide it up by one bin
+    auto shift = [&]() {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < n_e) Hq[(size_t)(base * n_e + k) * g.n_qpad] = (float)acc[0][k];
+#pragma unroll
+        for (int i = 0; i + 1 < W; ++i)
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) acc[i][k] = acc[i + 1][k];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) acc[W - 1][k] = 0.0;
+        ++base;
+    };
+    for (int r = 0; r < g.n_p; ++r) {
+        const size_t o = (size_t)a * g.n_p + r;
+        const int b0 = rb0[o];
+        while (base < b0) shift();
+        if (!active) continue;
+        const PathW pw = path_weight(g, p_pix, Ld, Bt, nx, ny, a, q, s_sorted[o]);
+        if (!(pw.w > 0.0)) continue;
+        double ef[KMAX + 1];
+#pragma unroll
+        for (int k = 0; k <= KMAX; ++k) ef[k] = k <= n_e ? erf((edges[k] - pw.ep) / s2) : 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const double wp = pw.w * rpm[o * W + i];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < n_e) acc[i][k] += wp * (0.5 * (ef[k + 1] - ef[k]));
+        }
+    }
+    while (base < n_pos) shift();
+}
+
 // counts[(a * n_pos + b) * n_e + k] += 1 per event inside a bin
 __global__ void k_bin_events(Geo g, int64_t n, const int32_t *__restrict__ angle, const float *__restrict__ u_bin,
                              const float *__restrict__ energy, int n_pos, const double *__restrict__ edges, int n_e,
@@ -105,6 +182,48 @@ hipError_t launch_binned_rows(const Geo &g, const Tables &t, int n_pos, const do
     hipLaunchKernelGGL(k_binned_rows, grid, dim3(256), 0, st, g, t.p_pix, t.cs, t.Ld, t.Bt, t.s_sorted, t.us_sorted,
                        n_pos, edges_dev, n_e, row_bin_dev, H);
     return hipGetLastError();
+}
+
+template <int W, int KMAX>
+void launch_rows_all(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,
+                     const int *angle_row0_dev, int *rb0, double *rpm, float *H, hipStream_t st) {
+    hipLaunchKernelGGL(k_rank_bin_masses<W>, dim3((unsigned)((g.n_p + 255) / 256), (unsigned)g.n_angles), dim3(256),
+                       0, st, g, t.us_sorted, n_pos, rb0, rpm);
+    hipLaunchKernelGGL((k_binned_rows_all<W, KMAX>), dim3((unsigned)(g.n_qpad / 64), (unsigned)g.n_angles), dim3(64),
+                       0, st, g, t.p_pix, t.cs, t.Ld, t.Bt, t.s_sorted, rb0, rpm, n_pos, edges_dev, n_e,
+                       angle_row0_dev, H);
+}
+
+// Rows of every bin, angle a's rows starting at angle_row0[a] in (position
+// bin, energy bin) order.  hipErrorNotSupported when a position response
+// spans more bins, or there are more energy bins, than the instantiated
+// windows hold (the caller then lists the bins for k_binned_rows).
+hipError_t launch_binned_rows_all(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,
+                                  const int *angle_row0_dev, float *H, hipStream_t st) {
+    if (!t.Ld) return hipErrorInvalidValue;
+    const double width = 2.0 * g.half_len / n_pos;
+    const int span = (int)ceil(6.0 * g.sig_u / width) + 2;   // bins a response can touch
+    const int W = span <= 8 ? 8 : span <= 16 ? 16 : 0;
+    if (W == 0 || n_e > (W == 8 ? 4 : 2)) return hipErrorNotSupported;
+    int *rb0 = nullptr;
+    double *rpm = nullptr;
+    const size_t na_np = (size_t)g.n_angles * g.n_p;
+    hipError_t e = hipMalloc(&rb0, sizeof(int) * na_np);
+    if (e == hipSuccess) e = hipMalloc(&rpm, sizeof(double) * na_np * W);
+    if (e == hipSuccess) {
+        // the fewest accumulators that hold the energy bins
+        if (W == 8 && n_e == 1) launch_rows_all<8, 1>(g, t, n_pos, edges_dev, n_e, angle_row0_dev, rb0, rpm, H, st);
+        else if (W == 8 && n_e == 2) launch_rows_all<8, 2>(g, t, n_pos, edges_dev, n_e, angle_row0_dev, rb0, rpm, H, st);
+        else if (W == 8) launch_rows_all<8, 4>(g, t, n_pos, edges_dev, n_e, angle_row0_dev, rb0, rpm, H, st);
+        else if (n_e == 1) launch_rows_all<16, 1>(g, t, n_pos, edges_dev, n_e, angle_row0_dev, rb0, rpm, H, st);
+        else launch_rows_all<16, 2>(g, t, n_pos, edges_dev, n_e, angle_row0_dev, rb0, rpm, H, st);
+        e = hipGetLastError();
+    }
+    // the scratch is released once the kernels are done
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(rb0);
+    hipFree(rpm);
+    return e;
 }
 
 hipError_t launch_bin_events(const Geo &g, const lmosem_events &ev, int n_pos, const double *edges_dev, int n_e,

@@ -72,6 +72,7 @@ struct Tables {
     // (training targets, binned rows)
     double *Ld = nullptr;        // [n_angles][n_p] L_a(p)
     double *Bt = nullptr;        // [n_p][n_p] B(q, s) at [s][q]
+    double *D_sorted = nullptr;  // [n_angles][n_p] detector mass of each rank's position response
     // learned-scatter contexts: exact near-field paths of each emission pixel
     float2 *band = nullptr;      // [n_angles][band_w][n_qpad] (alpha, beta), rank band_lo + k
     int *band_lo = nullptr;      // [n_angles][n_p] first rank of each pixel's band
@@ -79,8 +80,10 @@ struct Tables {
 };
 
 // ---- table build (tables.hip) ----
-hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
-                        std::string &err, int64_t &bytes);
+// build_base at create; build_paths before the first list-mode use
+hipError_t build_base(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes);
+hipError_t build_paths(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
+                       std::string &err, int64_t &bytes);
 
 // ---- event ingest (events.hip) ----
 struct EvSet;
@@ -98,6 +101,8 @@ hipError_t launch_binned_rows(const Geo &g, const Tables &t, int n_pos, const do
 hipError_t launch_image_max(const float *img, int n, float *out, hipStream_t st);
 hipError_t launch_emission_mask(const Geo &g, const float *mu, const float *img, double thr, int margin, float *mask,
                                 hipStream_t st);
+hipError_t launch_binned_rows_all(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,
+                                  const int *angle_row0_dev, float *H, hipStream_t st);
 hipError_t launch_bin_events(const Geo &g, const lmosem_events &ev, int n_pos, const double *edges_dev, int n_e,
                              float *counts, hipStream_t st);
 hipError_t launch_gather_counts(const float *counts, const int *row_bin, int n_rows, float *y, hipStream_t st);

@@ -236,54 +236,73 @@ __global__ void k_sens_reduce(Geo g, const double *__restrict__ sens_a, float *_
     sens_all[q] = (float)(g.acq_time * tot);
 }
 
-hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
-                        std::string &err, int64_t &bytes) {
+// Geometry every context needs at once: line integrals, scatter-point
+// factors, path ends ranked per angle and their detector-response masses.
+hipError_t build_base(const Geo &g, Tables &t, hipStream_t st, std::string &err, int64_t &bytes) {
     hipError_t e;
-    double *L = nullptr, *Bt = nullptr, *D_sorted = nullptr, *sens_a = nullptr;
+    auto fail = [&](const char *what, hipError_t code) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(code));
+        err = buf;
+        return code;
+    };
+#define CK(call, what) do { e = (call); if (e != hipSuccess) return fail(what, e); } while (0)
+    const size_t na_np = (size_t)g.n_angles * g.n_p;
+    CK(hipMalloc(&t.Ld, sizeof(double) * na_np), "alloc L");
+    if (g.scatter) CK(hipMalloc(&t.Bt, sizeof(double) * (size_t)g.n_p * g.n_p), "alloc B");
+    CK(hipMalloc(&t.D_sorted, sizeof(double) * na_np), "alloc D");
+    CK(hipMalloc(&t.s_sorted, sizeof(int) * na_np), "alloc ranks");
+    CK(hipMalloc(&t.us_sorted, sizeof(double) * na_np), "alloc positions");
+    CK(hipMalloc(&t.mu_sorted, sizeof(float) * na_np), "alloc positions");
+    CK(hipMalloc(&t.Ldet, sizeof(float) * na_np), "alloc line integrals");
+    CK(hipMalloc(&t.Lback, sizeof(float) * na_np), "alloc line integrals");
+    bytes = (int64_t)(na_np * (3 * sizeof(double) + sizeof(int) + 3 * sizeof(float)) +
+                      (g.scatter ? sizeof(double) * (size_t)g.n_p * g.n_p : 0));
+    hipLaunchKernelGGL(k_line_to_detector, dim3((unsigned)((na_np + 255) / 256)), dim3(256), 0, st, g, t.mu,
+                       t.p_pix, t.cs, t.Ld);
+    CK(hipGetLastError(), "line integrals");
+    hipLaunchKernelGGL(k_line_away, dim3((unsigned)((na_np + 255) / 256)), dim3(256), 0, st, g, t.mu, t.p_pix, t.cs,
+                       t.Ld, t.Ldet, t.Lback);
+    CK(hipGetLastError(), "line integrals away");
+    if (g.scatter) {
+        hipLaunchKernelGGL(k_scatter_points, dim3((g.n_p + 255) / 256, g.n_p), dim3(256), 0, st, g,
+                           t.mu, t.p_pix, t.Bt);
+        CK(hipGetLastError(), "scatter points");
+    }
+    hipLaunchKernelGGL(k_rank, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix,
+                       t.cs, t.mu, t.s_sorted, t.us_sorted, t.mu_sorted, t.D_sorted);
+    CK(hipGetLastError(), "rank");
+    CK(hipStreamSynchronize(st), "table build");
+#undef CK
+    return hipSuccess;
+}
+
+// What list-mode work needs on top of build_base: the per-subset
+// sensitivities, the primary weights, and the path table (store_paths) or the
+// near-field band (store_band).  Adds its device bytes to `bytes`.
+hipError_t build_paths(const Geo &g, Tables &t, bool store_paths, bool store_band, hipStream_t st,
+                       std::string &err, int64_t &bytes) {
+    hipError_t e;
+    double *sens_a = nullptr;
     int *band_len = nullptr;
     size_t nT = (size_t)g.n_angles * g.n_rpad * g.n_qpad;
     auto fail = [&](const char *what, hipError_t code) {
         char buf[256];
         snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(code));
         err = buf;
-        hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
+        hipFree(sens_a); hipFree(band_len);
         return code;
     };
 #define CK(call, what) do { e = (call); if (e != hipSuccess) return fail(what, e); } while (0)
-    CK(hipMalloc(&L, sizeof(double) * g.n_angles * g.n_p), "alloc L");
-    CK(hipMalloc(&Bt, sizeof(double) * (size_t)g.n_p * g.n_p), "alloc B");
-    CK(hipMalloc(&D_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc D");
     CK(hipMalloc(&sens_a, sizeof(double) * g.n_angles * g.n_qpad), "alloc sens_a");
-    CK(hipMalloc(&t.s_sorted, sizeof(int) * g.n_angles * g.n_p), "alloc ranks");
-    CK(hipMalloc(&t.us_sorted, sizeof(double) * g.n_angles * g.n_p), "alloc positions");
-    CK(hipMalloc(&t.mu_sorted, sizeof(float) * g.n_angles * g.n_p), "alloc positions");
     if (store_paths) CK(hipMalloc(&t.T, sizeof(float2) * nT), "alloc path table");
-    CK(hipMalloc(&t.Ldet, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
-    CK(hipMalloc(&t.Lback, sizeof(float) * g.n_angles * g.n_p), "alloc line integrals");
     CK(hipMalloc(&t.prim, sizeof(float) * g.n_angles * g.n_p), "alloc primary weights");
     CK(hipMalloc(&t.sens, sizeof(float) * g.n_subsets * g.n_qpad), "alloc sens");
     CK(hipMalloc(&t.sens_all, sizeof(float) * g.n_qpad), "alloc sens_all");
-    bytes = (int64_t)((store_paths ? sizeof(float2) * nT : 0) + 3 * sizeof(float) * g.n_angles * g.n_p +
-                      sizeof(int) * g.n_angles * g.n_p + sizeof(float) * g.n_angles * g.n_p +
-                      sizeof(double) * g.n_angles * g.n_p + sizeof(float) * (g.n_subsets + 1) * g.n_qpad);
-
-    int na_np = g.n_angles * g.n_p;
-    hipLaunchKernelGGL(k_line_to_detector, dim3((na_np + 255) / 256), dim3(256), 0, st, g, t.mu,
-                       t.p_pix, t.cs, L);
-    CK(hipGetLastError(), "line integrals");
-    hipLaunchKernelGGL(k_line_away, dim3((na_np + 255) / 256), dim3(256), 0, st, g, t.mu, t.p_pix, t.cs, L,
-                       t.Ldet, t.Lback);
-    CK(hipGetLastError(), "line integrals away");
-    if (g.scatter) {
-        hipLaunchKernelGGL(k_scatter_points, dim3((g.n_p + 255) / 256, g.n_p), dim3(256), 0, st, g,
-                           t.mu, t.p_pix, Bt);
-        CK(hipGetLastError(), "scatter points");
-    }
-    hipLaunchKernelGGL(k_rank, dim3((g.n_p + 255) / 256, g.n_angles), dim3(256), 0, st, g, t.p_pix,
-                       t.cs, t.mu, t.s_sorted, t.us_sorted, t.mu_sorted, D_sorted);
-    CK(hipGetLastError(), "rank");
+    bytes += (int64_t)((store_paths ? sizeof(float2) * nT : 0) + sizeof(float) * g.n_angles * g.n_p +
+                       sizeof(float) * (g.n_subsets + 1) * g.n_qpad);
     hipLaunchKernelGGL(k_path_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g,
-                       t.p_pix, t.cs, L, Bt, t.s_sorted, D_sorted, t.T, sens_a, t.prim);
+                       t.p_pix, t.cs, t.Ld, t.Bt, t.s_sorted, t.D_sorted, t.T, sens_a, t.prim);
     CK(hipGetLastError(), "path table");
     if (store_band && g.scatter) {
         CK(hipMalloc(&t.band_lo, sizeof(int) * g.n_angles * g.n_p), "alloc band ranges");
@@ -301,7 +320,7 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
         const size_t nb = (size_t)g.n_angles * t.band_w * g.n_qpad;
         CK(hipMalloc(&t.band, sizeof(float2) * nb), "alloc near-field table");
         hipLaunchKernelGGL(k_band_table, dim3((g.n_qpad + 63) / 64, g.n_angles), dim3(64), 0, st, g, t.band_w,
-                           t.p_pix, t.cs, L, Bt, t.s_sorted, t.band_lo, band_len, t.band);
+                           t.p_pix, t.cs, t.Ld, t.Bt, t.s_sorted, t.band_lo, band_len, t.band);
         CK(hipGetLastError(), "near-field table");
         bytes += (int64_t)(sizeof(float2) * nb + sizeof(int) * g.n_angles * g.n_p);
     }
@@ -309,16 +328,7 @@ hipError_t build_tables(const Geo &g, Tables &t, bool store_paths, bool store_ba
                        t.sens, t.sens_all);
     CK(hipGetLastError(), "sensitivity");
     CK(hipStreamSynchronize(st), "table build");
-    // kept for path weights evaluated on the fly (training targets, binned rows)
-    t.Ld = L;
-    L = nullptr;
-    bytes += (int64_t)(sizeof(double) * (size_t)g.n_angles * g.n_p);
-    if (g.scatter) {
-        t.Bt = Bt;
-        Bt = nullptr;
-        bytes += (int64_t)(sizeof(double) * (size_t)g.n_p * g.n_p);
-    }
-    hipFree(L); hipFree(Bt); hipFree(D_sorted); hipFree(sens_a); hipFree(band_len);
+    hipFree(sens_a); hipFree(band_len);
 #undef CK
     return hipSuccess;
 }

@@ -117,6 +117,39 @@ def test_binned_reconstruct_matches_oracle(tiny, dev):
     assert np.all(err <= tol), float(np.max(err / np.maximum(ref, 1e-300)))
 
 
+@pytest.mark.parametrize("n_pos,edges,masked", [(32, [100.0, 175.0], False), (48, EDGES, False),
+                                                 (128, [100.0, 175.0], False), (8, EDGES, True)])
+def test_binned_reconstruct_bin_widths_and_emission_set(tiny, dev, n_pos, edges, masked):
+    """Position bins from wider than to much narrower than the position
+    response (all-bins row kernel with 8- and 16-bin windows, and the per-bin
+    kernel beyond), and a context whose emission set is the activity support;
+    3 iterations against the oracle."""
+    L = _lib()
+    g, act, mu, ev, m = tiny["g"], tiny["act"], tiny["mu"], tiny["ev"], tiny["m"]
+    emission = torch.as_tensor((act > 0).astype(np.float32), device=dev) if masked else None
+    ctx = L.Context(dict(g, win_lo_kev=edges[0]), torch.as_tensor(mu, device=dev), emission=emission)
+    try:
+        n_cnt = 16 * n_pos * (len(edges) - 1)
+        counts = torch.empty(n_cnt, device=dev)
+        L.lmosem_bin_events(ctx.handle, L.events_to_device(ev, dev), n_pos, edges, counts)
+        img = torch.empty(mu.shape, device=dev)
+        L.lmosem_binned_reconstruct(ctx.handle, n_pos, edges, counts, 3, img)
+        got = img.cpu().numpy().ravel()
+        y = counts.cpu().numpy().astype(np.float64)
+    finally:
+        ctx.close()
+    mo = O.OracleModel(dict(g, win_lo_kev=edges[0]), mu)
+    keep = (act.ravel()[mo.support] > 0) if masked else np.ones(len(mo.support), bool)
+    H = O.binned_rows(mo, n_pos, edges)[:, keep]
+    row_angle = np.repeat(np.arange(16), n_pos * (len(edges) - 1))
+    ref = O.binned_os_mlem(H, y, row_angle, 4, 3, np.ones(int(keep.sum())))
+    q = mo.support[keep]
+    assert np.all(np.delete(got, q) == 0)
+    err = np.abs(got[q] - ref)
+    tol = np.where(ref >= 1e-2 * ref.max(), 1e-3 * ref, 1e-5 * ref.max())
+    assert np.all(err <= tol), float(np.max(err / np.maximum(ref, 1e-300)))
+
+
 def test_bin_events_drops_events_outside_the_bins(tiny, dev):
     """Photopeak-only bins on whole-spectrum events: only the events inside
     [143, 175] keV are counted."""
