@@ -466,6 +466,9 @@ lmosem_status lmosem_create_emission(const lmosem_config *cfg, const float *mu_d
     g.n_p = (int)p_pix.size();
     g.n_q = n_q;
     g.n_qpad = (g.n_q + 63) / 64 * 64;
+    // forward workgroups of 4 waves (fewer for an emission set of up to 192
+    // pixels, whose single workgroup would otherwise carry idle waves)
+    g.fwd_waves = std::min(4, g.n_qpad / 64);
     g.n_rpad = g.n_p + kRankPad;
     g.n_angles = cfg->n_angles; g.n_bins = cfg->n_bins; g.n_subsets = cfg->n_subsets;
     g.scatter = cfg->scatter_model != 0;

@@ -23,6 +23,7 @@ struct Geo {
                       // ordered with the emission pixels first)
     int n_qpad;       // n_q rounded up to a multiple of 64 (row stride of H and the table)
     int n_rpad;       // rank rows per angle in the path table: n_p + kRankPad
+    int fwd_waves;    // waves (64 emission pixels each) per forward-projection workgroup
     int n_angles, n_bins, n_subsets, scatter;
     double dx, bin_cm, half_len;
     double e0, kappa, sig_e, sig_u, win_lo, win_hi;
@@ -109,7 +110,7 @@ hipError_t launch_gather_counts(const float *counts, const int *row_bin, int n_r
 hipError_t launch_count_weights(const float *y, const float *inv, int n_rows, float *w, hipStream_t st);
 
 // ---- per sub-iteration kernels (osem.hip) ----
-int forward_groups(const Geo &g);
+__host__ __device__ int forward_groups(const Geo &g);
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
                           const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
                           float *pmean, int row_base, int n_rows, hipStream_t st);

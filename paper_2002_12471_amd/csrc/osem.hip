@@ -36,6 +36,21 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// Wave sum with DPP row operations (no LDS traffic): exchanges within quads
+// (lanes xor 1, xor 2), then mirrors within half-rows and rows give every
+// lane its 16-lane row sum, row 15 broadcasts add row 0 into row 1 and row 2
+// into row 3, and a lane-31 broadcast adds rows 0-1 into rows 2-3.  The total
+// is in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    return v;
+}
+
 // buffer resource word 3 of the gfx9 family (raw, untyped 32-bit access)
 constexpr int kBufferWord3 = 0x00020000;
 
@@ -82,8 +97,9 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
                                              int n_rows, float *Ks, float *red, int tid, int wave, int lane) {
     const int grp = logical / n_tiles;
     const Tile tl = tiles[logical - grp * n_tiles];
-    const int q = grp * 256 + tid;
-    const bool wave_on = grp * 256 + wave * 64 < g.n_qpad;
+    const int gw = 64 * g.fwd_waves;   // pixels per group = threads per workgroup
+    const int q = grp * gw + tid;
+    const bool wave_on = grp * gw + wave * 64 < g.n_qpad;
 
     float et[EV], acc[EV];
 #pragma unroll
@@ -107,7 +123,7 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         const int nr = min(kRch, tl.r1 - rc);
         const int nr4 = (nr + 3) & ~3;      // ranks are processed in groups of 4
         __syncthreads();
-        for (int idx = tid; idx < nr4 * EV; idx += 256) {
+        for (int idx = tid; idx < nr4 * EV; idx += gw) {
             const int r = idx / EV, e = idx - r * EV;
             float kv = 0.0f;
             if (e < tl.n && r < nr) {
@@ -152,12 +168,18 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
     const float fq = (wave_on && q < g.n_q) ? f[(size_t)tl.real * g.n_qpad + q] : 0.0f;
 #pragma unroll
     for (int e = 0; e < EV; ++e) {
-        const float v = wave_sum(fq * acc[e]);
-        if (lane == 0) red[wave * EV + e] = v;
+        const float v = wave_sum_to_lane63(fq * acc[e]);
+        if (lane == 63) red[wave * EV + e] = v;
     }
     __syncthreads();
     if (tid < tl.n) {
-        const float s = (red[tid] + red[EV + tid]) + (red[2 * EV + tid] + red[3 * EV + tid]);
+        float s;
+        if (g.fwd_waves == 4) {
+            s = (red[tid] + red[EV + tid]) + (red[2 * EV + tid] + red[3 * EV + tid]);
+        } else {
+            s = red[tid];
+            for (int w = 1; w < g.fwd_waves; ++w) s += red[w * EV + tid];
+        }
         pmean[(size_t)grp * n_rows + (tl.e0 - row_base) + tid] = s;
     }
 }
@@ -187,22 +209,22 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
                                                  int row_base, int n_rows) {
     __shared__ __align__(16) float Ks[kRch * EV];
     __shared__ float red[4 * EV];
-    const int n_groups = (g.n_qpad + 255) / 256;
+    const int n_groups = forward_groups(g);
     const int logical = xcd_logical(blockIdx.x, n_tiles * n_groups);
     const int tid = threadIdx.x;
     forward_item<EV>(g, tiles, n_tiles, logical, T, us_sorted, su, se, efac, f, H, pmean, row_base, n_rows, Ks,
                      red, tid, tid >> 6, tid & 63);
 }
 
-// pixel groups of the forward launch (one group per 256 pixels)
-int forward_groups(const Geo &g) { return (g.n_qpad + 255) / 256; }
+// pixel groups of the forward launch (one group per workgroup)
+__host__ __device__ int forward_groups(const Geo &g) { return (g.n_qpad + 64 * g.fwd_waves - 1) / (64 * g.fwd_waves); }
 
 template <int EV>
 static hipError_t launch_ev(const Geo &g, const Tables &t, const Tile *tiles, int n_tiles, const float *ev_u,
                             const float *ev_e, const float *efac, const float *f, float *H, float *pmean,
                             int row_base, int n_rows, hipStream_t st) {
     const int n_work = n_tiles * forward_groups(g);
-    hipLaunchKernelGGL(k_forward<EV>, dim3(n_work), dim3(256), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
+    hipLaunchKernelGGL(k_forward<EV>, dim3(n_work), dim3(64 * g.fwd_waves), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
                        ev_e, efac, f, H, pmean, row_base, n_rows);
     return hipGetLastError();
 }
