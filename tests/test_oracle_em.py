@@ -123,3 +123,34 @@ def test_binned_rows_tile_the_sensitivity():
     m = O.OracleModel(g, mu)
     H = O.binned_rows(m, 4, [100.0, 130.0, 175.0], angles=[1, 5, 9, 13])
     np.testing.assert_allclose(H.sum(axis=0), m.sensitivity(1), rtol=1e-10)
+
+
+def test_binned_mlem_approaches_list_mode_em_as_bins_shrink():
+    """Bins small enough to hold at most a few events each turn binned MLEM
+    into list-mode EM: with bins that tile the detector and the window,
+    sum_b H_b is the sensitivity and H_b / (H_b . f) tends to h_j / (h_j . f)
+    for the event j in bin b.  On an 8x8 disk with 4 angles and 150 events the
+    gap to the list-mode iterate falls as position and energy bins shrink."""
+    g = synth.Geometry(8, 8, 0.8, 8, 0.8, 4, n_subsets=1)
+    X, Y = synth.phantoms.pixel_centres(8, 8, 0.8)
+    mu = np.where(X ** 2 + Y ** 2 <= 3.0 ** 2, 0.15, 0.0).astype(np.float32)
+    act = np.where(X ** 2 + Y ** 2 <= 2.2 ** 2, 1.0, 0.0).astype(np.float32)
+    act[np.hypot(X - 0.8, Y) < 0.9] = 3.0
+    ev = synth.generate_events(g, act, mu, 150, 41)
+    gd = g.as_dict()
+    m = O.OracleModel(gd, mu)
+    n_it = 3
+    f_lm, _ = O.os_lm_mlem(m.system_matrix(ev), ev["angle"], m.sensitivity(-1)[None, :], n_it,
+                           np.ones(len(m.support)), 1)
+    gaps = []
+    for n_pos, n_e in ((8, 3), (32, 12), (128, 48)):
+        edges = np.linspace(gd["win_lo_kev"], gd["win_hi_kev"], n_e + 1)
+        H = O.binned_rows(m, n_pos, edges)
+        b = np.minimum((ev["u_bin"].astype(np.float64) * n_pos / gd["n_bins"]).astype(int), n_pos - 1)
+        k = np.clip(np.searchsorted(edges, ev["energy"].astype(np.float64), side="right") - 1, 0, n_e - 1)
+        y = np.bincount((ev["angle"] * n_pos + b) * n_e + k, minlength=H.shape[0]).astype(np.float64)
+        np.testing.assert_allclose(H.sum(axis=0), m.sensitivity(-1), rtol=1e-9)
+        f_b = O.binned_os_mlem(H, y, np.repeat(np.arange(4), n_pos * n_e), 1, n_it, np.ones(len(m.support)))
+        gaps.append(float(np.max(np.abs(f_b - f_lm)) / np.max(f_lm)))
+    assert gaps[0] > gaps[1] > gaps[2], gaps
+    assert gaps[2] < 0.25 * gaps[0] and gaps[2] < 0.02, gaps
