@@ -173,18 +173,42 @@ __global__ void k_input(const float *__restrict__ X, int n, uint16_t *__restrict
     }
 }
 
+// The elementwise training kernels work on tiles of 16 samples x 128 hidden
+// units (256 threads): the row-major [b][k] values are read and written
+// along k, and the transposed bf16 copy [k][b] goes through LDS so that it
+// is written along b (32 contiguous bytes per hidden unit).
+constexpr int kTileB = 16;
+
+template <typename F>
+__device__ __forceinline__ void tile_rows_and_transpose(int n, uint16_t *__restrict__ d, uint16_t *__restrict__ dt,
+                                                        F value) {
+    __shared__ uint16_t tile[kTileB][kHid + 2];
+    const int b0 = blockIdx.x * kTileB;
+    for (int i = threadIdx.x; i < kTileB * kHid; i += 256) {
+        const int bl = i / kHid, k = i % kHid, b = b0 + bl;
+        if (b < n) {
+            const uint16_t v = value((size_t)b * kHid + k, b, k);
+            d[(size_t)b * kHid + k] = v;
+            tile[bl][k] = v;
+        }
+    }
+    if (!dt) return;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTileB * kHid; i += 256) {
+        const int k = i / kTileB, bl = i % kTileB, b = b0 + bl;
+        if (b < n) dt[(size_t)k * n + b] = tile[bl][k];
+    }
+}
+
 // h = gelu(z + bias): z kept (with bias) for the backward pass; h in bf16,
 // optionally also transposed
-__global__ void k_bias_gelu(float *__restrict__ z, const float *__restrict__ bias, int n,
-                            uint16_t *__restrict__ h, uint16_t *__restrict__ ht) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)n * kHid) return;
-    const int k = (int)(idx % kHid);
-    const float v = z[idx] + bias[k];
-    z[idx] = v;
-    const uint16_t hb = f2bf(gelu(v));
-    h[idx] = hb;
-    if (ht) ht[(size_t)k * n + idx / kHid] = hb;
+__global__ __launch_bounds__(256) void k_bias_gelu(float *__restrict__ z, const float *__restrict__ bias, int n,
+                                                   uint16_t *__restrict__ h, uint16_t *__restrict__ ht) {
+    tile_rows_and_transpose(n, h, ht, [&](size_t idx, int, int k) {
+        const float v = z[idx] + bias[k];
+        z[idx] = v;
+        return f2bf(gelu(v));
+    });
 }
 
 // y[b] = sum_k h[b][k] w4[k] + b4  (one wave per sample group of 64)
@@ -219,26 +243,18 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
 }
 
 // output layer backward: d3[b][k] = dy[b] w4[k] gelu'(z3[b][k]) (bf16, both layouts)
-__global__ void k_out_back(const float *__restrict__ dy, const uint16_t *__restrict__ w4,
-                           const float *__restrict__ z3, int n, uint16_t *__restrict__ d, uint16_t *__restrict__ dt) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)n * kHid) return;
-    const int k = (int)(idx % kHid);
-    const size_t b = idx / kHid;
-    const uint16_t v = f2bf(dy[b] * bf2f(w4[k]) * gelu_grad(z3[idx]));
-    d[idx] = v;
-    dt[(size_t)k * n + b] = v;
+__global__ __launch_bounds__(256) void k_out_back(const float *__restrict__ dy, const uint16_t *__restrict__ w4,
+                                                  const float *__restrict__ z3, int n, uint16_t *__restrict__ d,
+                                                  uint16_t *__restrict__ dt) {
+    tile_rows_and_transpose(n, d, dt, [&](size_t idx, int b, int k) {
+        return f2bf(dy[b] * bf2f(w4[k]) * gelu_grad(z3[idx]));
+    });
 }
 
 // hidden layer backward: d[b][k] = dh[b][k] gelu'(z[b][k]) (bf16, both layouts)
-__global__ void k_gelu_back(const float *__restrict__ dh, const float *__restrict__ z, int n,
-                            uint16_t *__restrict__ d, uint16_t *__restrict__ dt) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)n * kHid) return;
-    const int k = (int)(idx % kHid);
-    const uint16_t v = f2bf(dh[idx] * gelu_grad(z[idx]));
-    d[idx] = v;
-    dt[(size_t)k * n + idx / kHid] = v;
+__global__ __launch_bounds__(256) void k_gelu_back(const float *__restrict__ dh, const float *__restrict__ z, int n,
+                                                   uint16_t *__restrict__ d, uint16_t *__restrict__ dt) {
+    tile_rows_and_transpose(n, d, dt, [&](size_t idx, int, int) { return f2bf(dh[idx] * gelu_grad(z[idx])); });
 }
 
 // bias gradients: column sums of the transposed bf16 deltas dt[k][b]; the
@@ -304,16 +320,18 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 // operands leaves the product unchanged): exactly the rows lane l holds of the
 // previous layer's output blocks 2 kb and 2 kb + 1, so activations stay in
 // registers from layer to layer.  The weights, pre-permuted into A-operand
-// lane order, the biases and the output row sit in LDS (75.8 KB: two
-// workgroups per CU); each wave takes 32 samples per step (146 VGPRs, so
-// two waves per SIMD).
+// lane order, the biases and the output row sit in LDS (75.8 KB), shared by
+// the twelve waves of one workgroup per CU; each wave takes 32 samples per
+// step (148 VGPRs, so three waves per SIMD).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
 constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
 constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
 constexpr int kFB = 4 * kHid + 1;                // b1 b2 b3, w4 (bf16 values), b4
 constexpr int kFusedNB = 2;                      // 16-sample column blocks per wave
-constexpr int kFusedTile = 4 * 16 * kFusedNB;    // samples per workgroup step
+constexpr int kFusedWaves = 12;                  // one workgroup per CU: 3 waves per SIMD share one LDS copy
+constexpr int kFusedThreads = 64 * kFusedWaves;
+constexpr int kFusedTile = kFusedWaves * 16 * kFusedNB;   // samples per workgroup step
 // gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
 // rewritten with one exp2 and one reciprocal
 constexpr float kGeluK0 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;
@@ -383,15 +401,15 @@ __device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *_
         for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ fw, const float *__restrict__ fb,
+__global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__restrict__ fw, const float *__restrict__ fb,
                                                  const float *__restrict__ X, int64_t n, float *__restrict__ y) {
     __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
     __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(fw);
         uint4 *dst = reinterpret_cast<uint4 *>(s_w);
-        for (int i = threadIdx.x; i < kFWTotal / 8; i += 256) dst[i] = src[i];
-        for (int i = threadIdx.x; i < kFB; i += 256) s_b[i] = fb[i];
+        for (int i = threadIdx.x; i < kFWTotal / 8; i += kFusedThreads) dst[i] = src[i];
+        for (int i = threadIdx.x; i < kFB; i += kFusedThreads) s_b[i] = fb[i];
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -563,6 +581,7 @@ hipError_t net_get_params(Net *n, float *host) {
 }
 
 static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
+static inline unsigned tiles(int nb) { return (unsigned)((nb + kTileB - 1) / kTileB); }
 
 // forward pass of one batch of nb samples (nb a multiple of 16); keeps the
 // activations for the backward pass when train is set
@@ -571,13 +590,13 @@ static hipError_t forward_batch(Net &n, const float *X, int nb, float *y, bool t
     hipStream_t st = n.st;
     hipLaunchKernelGGL(k_input, dim3(blocks(nb)), dim3(256), 0, st, X, nb, n.xb, train ? n.xt : nullptr);
     if ((e = gemm_nt(n.xb, kInPad, n.nb.w1t, kInPad, n.z1, kHid, nb, kHid, kInPad, false, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks((size_t)nb * kHid)), dim3(256), 0, st, n.z1, n.p + kOffB1, nb, n.h1,
+    hipLaunchKernelGGL(k_bias_gelu, dim3(tiles(nb)), dim3(256), 0, st, n.z1, n.p + kOffB1, nb, n.h1,
                        train ? n.h1t : nullptr);
     if ((e = gemm_nt(n.h1, kHid, n.nb.w2t, kHid, n.z2, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks((size_t)nb * kHid)), dim3(256), 0, st, n.z2, n.p + kOffB2, nb, n.h2,
+    hipLaunchKernelGGL(k_bias_gelu, dim3(tiles(nb)), dim3(256), 0, st, n.z2, n.p + kOffB2, nb, n.h2,
                        train ? n.h2t : nullptr);
     if ((e = gemm_nt(n.h2, kHid, n.nb.w3t, kHid, n.z3, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks((size_t)nb * kHid)), dim3(256), 0, st, n.z3, n.p + kOffB3, nb, n.h3,
+    hipLaunchKernelGGL(k_bias_gelu, dim3(tiles(nb)), dim3(256), 0, st, n.z3, n.p + kOffB3, nb, n.h3,
                        train ? n.h3t : nullptr);
     hipLaunchKernelGGL(k_output, dim3(blocks(nb)), dim3(256), 0, st, n.h3, n.nb.w4, n.p, nb, y);
     return hipGetLastError();
@@ -587,17 +606,16 @@ static hipError_t forward_batch(Net &n, const float *X, int nb, float *y, bool t
 static hipError_t backward_batch(Net &n, const float *dy, int nb) {
     hipError_t e;
     hipStream_t st = n.st;
-    const size_t nh = (size_t)nb * kHid;
-    hipLaunchKernelGGL(k_out_back, dim3(blocks(nh)), dim3(256), 0, st, dy, n.nb.w4, n.z3, nb, n.d3, n.d3t);
+    hipLaunchKernelGGL(k_out_back, dim3(tiles(nb)), dim3(256), 0, st, dy, n.nb.w4, n.z3, nb, n.d3, n.d3t);
     // dW3[in][out] = h2t . d3t ; dh2 = d3 . W3
     if ((e = gemm_nt(n.h2t, nb, n.d3t, nb, n.g + kOffW3, kHid, kHid, kHid, nb, false, st, n.split)) != hipSuccess)
         return e;
     if ((e = gemm_nt(n.d3, kHid, n.nb.w3, kHid, n.dh, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gelu_back, dim3(blocks(nh)), dim3(256), 0, st, n.dh, n.z2, nb, n.d2, n.d2t);
+    hipLaunchKernelGGL(k_gelu_back, dim3(tiles(nb)), dim3(256), 0, st, n.dh, n.z2, nb, n.d2, n.d2t);
     if ((e = gemm_nt(n.h1t, nb, n.d2t, nb, n.g + kOffW2, kHid, kHid, kHid, nb, false, st, n.split)) != hipSuccess)
         return e;
     if ((e = gemm_nt(n.d2, kHid, n.nb.w2, kHid, n.dh, kHid, nb, kHid, kHid, false, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gelu_back, dim3(blocks(nh)), dim3(256), 0, st, n.dh, n.z1, nb, n.d1, n.d1t);
+    hipLaunchKernelGGL(k_gelu_back, dim3(tiles(nb)), dim3(256), 0, st, n.dh, n.z1, nb, n.d1, n.d1t);
     if ((e = gemm_nt(n.xt, nb, n.d1t, nb, n.gw1, kHid, kInPad, kHid, nb, false, st, n.split)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_copy_w1_grad, dim3(blocks(kIn * kHid)), dim3(256), 0, st, n.gw1, n.g);
     hipLaunchKernelGGL(k_bias_grads, dim3(4 * kHid + 1), dim3(256), 0, st, n.d1t, n.d2t, n.d3t, n.h3t, dy, nb, n.g);
@@ -607,8 +625,8 @@ static hipError_t backward_batch(Net &n, const float *dy, int nb) {
 hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int64_t tiles = (count + kFusedTile - 1) / kFusedTile;
-    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2 * 256);   // two workgroups per CU
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, st, n->fw, n->fb, X, count, y);
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256);   // one workgroup per CU
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(kFusedThreads), 0, st, n->fw, n->fb, X, count, y);
     return hipGetLastError();
 }
 
