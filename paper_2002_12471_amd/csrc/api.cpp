@@ -69,7 +69,7 @@ struct lmosem_evset {
 
 namespace {
 
-constexpr int64_t kPairCap = 1 << 20;   // (event, pixel) pairs per surrogate network batch
+constexpr int64_t kPairCap = 1 << 22;   // (event, pixel) pairs per surrogate network batch (148 MB of inputs)
 
 lmosem_status set_err(lmosem_ctx *c, lmosem_status s, const std::string &msg) {
     if (c) {

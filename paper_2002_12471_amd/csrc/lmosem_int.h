@@ -75,7 +75,7 @@ struct Tables {
     double *Bt = nullptr;        // [n_p][n_p] B(q, s) at [s][q]
     double *D_sorted = nullptr;  // [n_angles][n_p] detector mass of each rank's position response
     // learned-scatter contexts: exact near-field paths of each emission pixel
-    float2 *band = nullptr;      // [n_angles][band_w][n_qpad] (alpha, beta), rank band_lo + k
+    float2 *band = nullptr;      // [n_angles][n_qpad][band_w] (alpha, beta), rank band_lo + k
     int *band_lo = nullptr;      // [n_angles][n_p] first rank of each pixel's band
     int band_w = 0;              // longest band
 };

@@ -196,14 +196,10 @@ __global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_
 }
 
 // Inference, step 1: for rows [j0, j0 + rows) of the sub-iteration and every
-// emission pixel q, the exact primary and near-field scatter terms into H, the
-// near-field flag (|u - u_q| < 3 sig_u) and the network inputs.
-__global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ band, int band_w,
-                             const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
-                             const float *__restrict__ su, const float *__restrict__ se,
-                             const float *__restrict__ efac, const float4 *__restrict__ col,
-                             const int2 *__restrict__ rr, int row_base, int j0, int rows, float *__restrict__ H,
-                             uint8_t *__restrict__ near, float *__restrict__ X) {
+// emission pixel q, the network inputs; H and the near-field flag start at 0.
+__global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
+                             const float *__restrict__ se, const float4 *__restrict__ col, int row_base, int j0,
+                             int rows, float *__restrict__ H, uint8_t *__restrict__ near, float *__restrict__ X) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch < 2^31
     if (k >= rows * g.n_q) return;
     const int jr = j0 + k / g.n_q, q = k % g.n_q;
@@ -211,38 +207,69 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const float2 *__restrict__ ba
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
     const float et = se[j];   // E - e_c
-    double uq, dq;
-    pixel_frame(g, st, q, a, uq, dq);
-    const double reach = 3.0 * g.sig_u;
-    const bool is_near = fabs(u - uq) < reach;
-    float h = 0.0f;
-    if (is_near) {
-        const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
-        const float beta0 = (float)(2.0 * g.c2 * (g.e0 - g.e_c));
-        h = k_resp_f((float)(u - uq), inv2s2) *
-            __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
-        // near field: the ends the event reaches, all inside q's band
-        const double *us = st.us_sorted + (size_t)a * g.n_p;
-        const int lo = band_lo[(size_t)a * g.n_p + q];
-        const float2 *bq = band + (size_t)a * band_w * g.n_qpad + q;
-        const int2 r = rr[j - row_base];
-        const int b0 = max(r.x - lo, 0), b1 = min(r.y - lo, band_w);
-        for (int b = b0; b < b1; ++b) {
-            const float2 ab = bq[(size_t)b * g.n_qpad];
-            h = fmaf(k_resp_f((float)(u - us[lo + b]), inv2s2), __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)), h);
-        }
-        h *= efac[j];
-    }
-    H[(size_t)jr * g.n_qpad + q] = h;
-    near[k] = is_near ? 1 : 0;
+    H[(size_t)jr * g.n_qpad + q] = 0.0f;
+    near[k] = 0;
     float x[8];
     features(g, st, q, a, u, (double)et + g.e_c, col[j - row_base], x);
-    float *xo = X + (size_t)k * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) xo[i] = x[i];
+    float4 *xo = reinterpret_cast<float4 *>(X + (size_t)k * 8);
+    xo[0] = make_float4(x[0], x[1], x[2], x[3]);
+    xo[1] = make_float4(x[4], x[5], x[6], x[7]);
 }
 
-// Inference, step 3: add the network's scatter estimate to the far-field pairs.
+// Inference, step 2: the near field, exact.  The emission pixels within the
+// event's own position response (|u - u_q| < 3 sig_u) are exactly the
+// emission pixels among the path ends the event reaches (its rank range), so
+// one block per event row walks that range: each group of 16 lanes takes one
+// such pixel q, its lanes share the scatter terms of the ends the event
+// reaches (all inside q's band, stored contiguously per q, so the group's
+// loads are contiguous), and the group's first lane adds the primary term,
+// writes H and flags the pair as near.
+__global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const float2 *__restrict__ band, int band_w,
+                                                   const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
+                                                   const float *__restrict__ su, const float *__restrict__ se,
+                                                   const float *__restrict__ efac, const int2 *__restrict__ rr,
+                                                   int row_base, int j0, int rows, float *__restrict__ H,
+                                                   uint8_t *__restrict__ near) {
+    const int lr = blockIdx.x;   // row within the batch
+    if (lr >= rows) return;
+    const int jr = j0 + lr, j = row_base + jr;
+    const int a = ev_angle[j];
+    const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
+    const float et = se[j];
+    const int2 r = rr[jr];
+    const double *us = st.us_sorted + (size_t)a * g.n_p;
+    const int *ss = st.s_sorted + (size_t)a * g.n_p;
+    const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
+    const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
+    // every group runs the same number of passes, so the 16-lane sums below
+    // always see all of their lanes
+    for (int rank0 = r.x; rank0 < r.y; rank0 += 16) {
+        const int rank = rank0 + grp;
+        const int q = rank < r.y ? ss[rank] : g.n_q;
+        float h = 0.0f;
+        if (q < g.n_q) {
+            const int lo = band_lo[(size_t)a * g.n_p + q];
+            const float2 *bq = band + ((size_t)a * g.n_qpad + q) * band_w;
+            const int b0 = max(r.x - lo, 0), b1 = min(r.y - lo, band_w);
+            for (int b = b0 + l; b < b1; b += 16) {
+                const float2 ab = bq[b];
+                h = fmaf(k_resp_f((float)(u - us[lo + b]), inv2s2), __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)), h);
+            }
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) h += __shfl_xor(h, off, 64);
+        if (l == 0 && q < g.n_q) {
+            const float beta0 = (float)(2.0 * g.c2 * (g.e0 - g.e_c));
+            h += k_resp_f((float)(u - us[rank]), inv2s2) *
+                 __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
+            H[(size_t)jr * g.n_qpad + q] = h * efac[j];
+            near[(size_t)lr * g.n_q + q] = 1;
+        }
+    }
+}
+
+// Inference, step 4 (after the network, step 3): add the network's scatter
+// estimate to the far-field pairs.
 __global__ void k_surr_add(Geo g, int j0, int rows, const uint8_t *__restrict__ near, const float *__restrict__ y,
                            float *__restrict__ H) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,8 +322,11 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
     for (int j0 = 0; j0 < rows; j0 += rows_per) {
         const int nr = std::min(rows_per, rows - j0);
         const int64_t pairs = (int64_t)nr * g.n_q;
-        hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, t.band,
-                           t.band_w, t.band_lo, ev_angle, su, se, efac, col4, rr, row_base, j0, nr, H, near, X);
+        hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
+                           se, col4, row_base, j0, nr, H, near, X);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_surr_near, dim3((unsigned)nr), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
+                           ev_angle, su, se, efac, rr, row_base, j0, nr, H, near);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = net_forward(net, X, pairs, y, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, near,

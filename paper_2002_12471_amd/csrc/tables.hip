@@ -197,7 +197,7 @@ __global__ void k_band_range(Geo g, const int *__restrict__ p_pix, const double 
     band_len[(size_t)a * g.n_p + q] = lo2 - lo;
 }
 
-// Near-field table band[a][k][q] = code of rank band_lo[a][q] + k (the
+// Near-field table band[a][q][k] = code of rank band_lo[a][q] + k (the
 // primary path s == q and slots past the band never contribute).
 __global__ void k_band_table(Geo g, int band_w, const int *__restrict__ p_pix, const double *__restrict__ cs,
                              const double *__restrict__ L, const double *__restrict__ Bt,
@@ -206,7 +206,7 @@ __global__ void k_band_table(Geo g, int band_w, const int *__restrict__ p_pix, c
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int a = blockIdx.y;
     if (q >= g.n_qpad) return;
-    float2 *out = band + (size_t)a * band_w * g.n_qpad + q;
+    float2 *out = band + ((size_t)a * g.n_qpad + q) * band_w;
     const int lo = q < g.n_q ? band_lo[(size_t)a * g.n_p + q] : 0;
     const int len = q < g.n_q ? band_len[(size_t)a * g.n_p + q] : 0;
     const double nx = cs[2 * a], ny = cs[2 * a + 1];
@@ -217,7 +217,7 @@ __global__ void k_band_table(Geo g, int band_w, const int *__restrict__ p_pix, c
             const int s = s_sorted[(size_t)a * g.n_p + lo + k];
             if (s != q) code = path_code(g, path_weight(g, p_pix, L, Bt, nx, ny, a, q, s), log2_gnorm);
         }
-        out[(size_t)k * g.n_qpad] = code;
+        out[k] = code;
     }
 }
 

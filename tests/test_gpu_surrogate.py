@@ -186,6 +186,75 @@ def test_near_field_is_exact(dev):
     np.testing.assert_allclose(got[ok], ref[ok], rtol=1e-4)
 
 
+def _zero_scatter_net(L):
+    """A network whose scatter estimate is 0 (y = -20 is below the target floor)."""
+    p = synth.mlp_init_params(1)
+    for k in p:
+        p[k] = np.zeros_like(p[k])
+    p["b4"] = np.array([-20.0], np.float32)
+    return L.lmosem_net_create(p)
+
+
+def test_near_field_is_exact_brain64(dev):
+    """The near field at the 64x64 brain's size (bands of ~200 path ends,
+    several passes of each 16-lane group): with a zero network, 200 events'
+    means against the exact primary and near-field scatter sums."""
+    L = _lib()
+    w = synth.workload("brain64")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    ev = synth.workload_events(w, n_events=200)
+    net = _zero_scatter_net(L)
+    try:
+        ctx = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev))
+        L.lmosem_set_surrogate(ctx.handle, net)
+        got = ctx.forward(L.events_to_device(ev, dev), torch.as_tensor(act, device=dev)).double().cpu().numpy()
+        ctx.close()
+    finally:
+        L.lmosem_net_destroy(net)
+    m1 = O.OracleModel(g, mu)
+    n, dx = int(g["nx"]), float(g["pixel_cm"])
+    sig_u = float(g["fwhm_u_cm"]) / (2 * np.sqrt(2 * np.log(2)))
+    idx = (np.arange(n) - (n - 1) / 2) * dx
+    sup = np.flatnonzero((mu.ravel() > 0) & (act.ravel() > 0))
+    xs, ys = idx[sup % n], idx[sup // n]
+    ref = np.zeros(len(got))
+    for j in range(len(got)):
+        a, u, e = int(ev["angle"][j]), float(m1.u_cm(ev["u_bin"][j])), float(ev["energy"][j])
+        th = float(g.get("angle0_rad", 0.0)) + 2 * np.pi * a / int(g["n_angles"])
+        uq = -np.sin(th) * xs + np.cos(th) * ys
+        for pix in sup[np.abs(u - uq) < 3 * sig_u]:
+            ref[j] += act.flat[pix] * m1.h(int(pix), a, u, e)
+    ok = ref > 1e-6 * ref.max()
+    assert ok.sum() > 150
+    np.testing.assert_allclose(got[ok], ref[ok], rtol=1e-4)
+
+
+def test_surrogate_rows_do_not_depend_on_batching(dev):
+    """All 200k brain64 events (287M (event, pixel) pairs, many network
+    batches) against the same events forward-projected a few hundred at a
+    time (one batch each): every (event, pixel) value is computed on its own,
+    so the means agree bit for bit."""
+    L = _lib()
+    w = synth.workload("brain64")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    ev = synth.workload_events(w)
+    net = L.lmosem_net_create(synth.mlp_init_params(9))
+    try:
+        ctx = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev))
+        L.lmosem_set_surrogate(ctx.handle, net)
+        img = torch.as_tensor(act, device=dev)
+        full = ctx.forward(L.events_to_device(ev, dev), img).cpu().numpy()
+        for lo in (0, 98_765, 199_600):
+            part = {k: ev[k][lo:lo + 400] for k in ("angle", "u_bin", "energy")}
+            got = ctx.forward(L.events_to_device(part, dev), img).cpu().numpy()
+            np.testing.assert_array_equal(got, full[lo:lo + 400])
+        ctx.close()
+    finally:
+        L.lmosem_net_destroy(net)
+
+
 def train_surrogate(L, dev, n_maps=48, per_map=8192, epochs=30, seed=404):
     """Samples from random elliptical maps on the tiny grid, then Adam."""
     w = synth.workload("surrogate_maps")
