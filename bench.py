@@ -300,16 +300,18 @@ def bench_study(args, L, torch, np, synth):
     window's events reconstructed (10 iterations, 8 subsets, all realisations
     in one batch) with first-order scatter modelled and with primary paths
     only, and binned variants (64 position bins, 1-3 energy bins); per
-    realisation the caudate and putamen uptake ratios (region mean over the
-    brain-background mean; truth 8) and the image NRMSE against the truth
-    after scaling to the truth's brain mean."""
+    realisation the caudate and putamen uptakes (normalised RMSE over the
+    realisations after every iteration), their ratios to the brain-background
+    mean (truth 8) and the image NRMSE against the truth after scaling to the
+    truth's brain mean."""
     dev = torch.device("cuda:0")
     w = synth.workload("brain64")
     g = w.geom.as_dict()
     act, mu = synth.phantom(w)
     R = args.realisations or 16
     log(f"generating {R} realisations")
-    parts = [synth.workload_events(w, realisation=r) for r in range(R)]
+    n_ev = args.study_events or w.n_events
+    parts = [synth.workload_events(w, realisation=r, n_events=n_ev) for r in range(R)]
     caud, put = synth.striatal_masks(w.geom)
     brain = act > 0
     bg = brain & ~caud & ~put
@@ -318,6 +320,52 @@ def bench_study(args, L, torch, np, synth):
     truth = torch.as_tensor(act, device=dev).double()
     mu_d = torch.as_tensor(mu, device=dev)
     rows, events_done, t_recon = [], 0, 0.0
+    start = np.broadcast_to((mu > 0).astype(np.float32), (R,) + mu.shape).copy()
+
+    def score(by_iter, counts, sens_all):
+        """Task measures of one configuration from its images after each
+        iteration (by_iter[t][r] = image of realisation r after t + 1
+        iterations).  Uptake = mean activity in the region; its truth for
+        realisation r is the true region mean scaled so that the true image
+        predicts the realisation's counts (counts[r] = sum_q sens_q f_q, the
+        preset-count scale), and the normalised RMSE over realisations of the
+        uptake is reported per iteration (the paper's figure of merit).  At
+        the last iteration also the ratio of each region's mean to the brain
+        background mean (truth 8) and the image NRMSE after scaling to the
+        truth's brain mean."""
+        scale = float((sens_all * truth).sum())
+        out = {}
+        for k, m in masks.items():
+            u_true = float(truth[m].mean())
+            curve = []
+            for imgs in by_iter:
+                e = [float(imgs[r][m].double().mean()) / (counts[r] / scale * u_true) - 1.0 for r in range(R)]
+                curve.append(float(np.sqrt(np.mean(np.square(e)))))
+            out[f"{k}_uptake_nrmse_by_iter"] = curve
+        ratios = {k: [] for k in masks}
+        nrmse = []
+        for r in range(R):
+            f = by_iter[-1][r].double()
+            bgm = float(f[bg_t].mean())
+            for k, m in masks.items():
+                ratios[k].append(float(f[m].mean()) / bgm)
+            fs = f * (float(truth[brain_t].mean()) / float(f[brain_t].mean()))
+            nrmse.append(float(((fs - truth)[brain_t] ** 2).sum().sqrt() / (truth[brain_t] ** 2).sum().sqrt()))
+        out["nrmse_mean"], out["nrmse_std"] = float(np.mean(nrmse)), float(np.std(nrmse))
+        for k, v in ratios.items():
+            out[f"{k}_ratio_mean"] = float(np.mean(v))
+            out[f"{k}_ratio_std"] = float(np.std(v))
+            out[f"{k}_ratio_bias_pct"] = 100.0 * (float(np.mean(v)) - 8.0) / 8.0
+        return out
+
+    def report(row):
+        rows.append(row)
+        log(f"{row['window_kev']} keV, {row['model'][:60]}: caudate {row['caudate_ratio_mean']:.2f} +- "
+            f"{row['caudate_ratio_std']:.2f}, putamen {row['putamen_ratio_mean']:.2f} +- "
+            f"{row['putamen_ratio_std']:.2f}, image nrmse {row['nrmse_mean']:.3f}, uptake nrmse (it 10) "
+            f"{row['caudate_uptake_nrmse_by_iter'][-1]:.3f} / {row['putamen_uptake_nrmse_by_iter'][-1]:.3f}")
+
+    sens_whole = None
     for lo in (143.0, 120.0, 100.0):
         sel = [p["energy"] >= lo for p in parts]
         ev = {k: np.concatenate([p[k][m] for p, m in zip(parts, sel)]) for k in ("angle", "u_bin", "energy")}
@@ -326,73 +374,57 @@ def bench_study(args, L, torch, np, synth):
         evd = L.events_to_device(ev, dev)
         for model, name in ((1, "first-order scatter"), (0, "primary only")):
             ctx = L.Context(dict(g, win_lo_kev=lo, scatter_model=model), mu_d)
+            sens_all = ctx.sensitivity(-1).double()
+            if lo == 100.0 and model == 1:
+                sens_whole = sens_all
+            evs = L.lmosem_events_load(ctx.handle, evd, offsets)
+            img = torch.as_tensor(start, device=dev)
+            by_iter = []
             torch.cuda.synchronize()
             t0 = time.time()
-            imgs = ctx.reconstruct(evd, 10, batch_offsets=offsets).double()
+            for _ in range(10):
+                L.lmosem_iterate(ctx.handle, evs, 1, img, n_real=R)
+                by_iter.append(img.clone())
             torch.cuda.synchronize()
             t_recon += time.time() - t0
             events_done += 10 * sum(sizes)
+            L.lmosem_events_free(evs)
             ctx.close()
-            ratios = {k: [] for k in masks}
-            nrmse = []
-            for r in range(R):
-                f = imgs[r]
-                bgm = float(f[bg_t].mean())
-                for k, m in masks.items():
-                    ratios[k].append(float(f[m].mean()) / bgm)
-                fs = f * (float(truth[brain_t].mean()) / float(f[brain_t].mean()))
-                nrmse.append(float(((fs - truth)[brain_t] ** 2).sum().sqrt() / (truth[brain_t] ** 2).sum().sqrt()))
-            row = {"window_kev": [lo, g["win_hi_kev"]], "model": name, "events_per_realisation": int(np.mean(sizes)),
-                   "nrmse_mean": float(np.mean(nrmse)), "nrmse_std": float(np.std(nrmse))}
-            for k, v in ratios.items():
-                row[f"{k}_ratio_mean"] = float(np.mean(v))
-                row[f"{k}_ratio_std"] = float(np.std(v))
-                row[f"{k}_ratio_bias_pct"] = 100.0 * (float(np.mean(v)) - 8.0) / 8.0
-            rows.append(row)
-            log(f"window {lo}-{g['win_hi_kev']} keV, {name}: caudate {row['caudate_ratio_mean']:.2f}"
-                f" +- {row['caudate_ratio_std']:.2f}, putamen {row['putamen_ratio_mean']:.2f}"
-                f" +- {row['putamen_ratio_std']:.2f}, nrmse {row['nrmse_mean']:.3f}")
+            report({"window_kev": [lo, g["win_hi_kev"]], "model": name + ", list mode",
+                    "events_per_realisation": int(np.mean(sizes)), **score(by_iter, sizes, sens_all)})
     # binned variants of the whole-spectrum data: 64 position bins (two detector
     # bins each) and 1, 2 or 3 energy bins, first-order scatter modelled
     t_bin = 0.0
     for edges in ([143.0, 175.0], [100.0, 143.0, 175.0], [100.0, 120.0, 143.0, 175.0]):
         ctx = L.Context(dict(g, win_lo_kev=edges[0], scatter_model=1), mu_d)
+        sens_all = ctx.sensitivity(-1).double()
         n_pos = g["n_bins"] // 2
         counts = torch.empty(g["n_angles"] * n_pos * (len(edges) - 1), device=dev)
-        img = torch.empty(mu.shape, device=dev)
-        ratios = {k: [] for k in masks}
-        nrmse = []
-        n_counts = []
+        per_r, n_counts = [], []
         for r in range(R):
             L.lmosem_bin_events(ctx.handle, L.events_to_device(parts[r], dev), n_pos, edges, counts)
             n_counts.append(float(counts.sum()))
+            series, prev = [], None
             torch.cuda.synchronize()
             t0 = time.time()
-            L.lmosem_binned_reconstruct(ctx.handle, n_pos, edges, counts, 10, img)
+            for _ in range(10):
+                img = torch.empty(mu.shape, device=dev)
+                L.lmosem_binned_reconstruct(ctx.handle, n_pos, edges, counts, 1, img, init=prev)
+                series.append(img)
+                prev = img
             torch.cuda.synchronize()
             t_bin += time.time() - t0
-            f = img.double()
-            bgm = float(f[bg_t].mean())
-            for k, m in masks.items():
-                ratios[k].append(float(f[m].mean()) / bgm)
-            fs = f * (float(truth[brain_t].mean()) / float(f[brain_t].mean()))
-            nrmse.append(float(((fs - truth)[brain_t] ** 2).sum().sqrt() / (truth[brain_t] ** 2).sum().sqrt()))
+            per_r.append(series)
         ctx.close()
-        row = {"window_kev": [edges[0], edges[-1]], "model": f"first-order scatter, binned: {n_pos} position x "
-               f"{len(edges) - 1} energy bins {edges}", "events_per_realisation": int(np.mean(n_counts)),
-               "nrmse_mean": float(np.mean(nrmse)), "nrmse_std": float(np.std(nrmse))}
-        for k, v in ratios.items():
-            row[f"{k}_ratio_mean"] = float(np.mean(v))
-            row[f"{k}_ratio_std"] = float(np.std(v))
-            row[f"{k}_ratio_bias_pct"] = 100.0 * (float(np.mean(v)) - 8.0) / 8.0
-        rows.append(row)
-        log(f"binned {edges}: caudate {row['caudate_ratio_mean']:.2f} +- {row['caudate_ratio_std']:.2f}, putamen "
-            f"{row['putamen_ratio_mean']:.2f} +- {row['putamen_ratio_std']:.2f}, nrmse {row['nrmse_mean']:.3f}")
+        by_iter = [torch.stack([per_r[r][t] for r in range(R)]) for t in range(10)]
+        report({"window_kev": [edges[0], edges[-1]], "model": f"first-order scatter, binned: {n_pos} position x "
+                f"{len(edges) - 1} energy bins {edges}", "events_per_realisation": int(np.mean(n_counts)),
+                **score(by_iter, n_counts, sens_all)})
     # list mode over the whole spectrum with the estimate confined to a crude
     # boundary from each realisation's own binned OS-MLEM (one context per
     # realisation, since the boundary differs)
     gw = dict(g, win_lo_kev=100.0, scatter_model=1)
-    ratios, nrmse, n_em, cover, t_front, t_em = {k: [] for k in masks}, [], [], [], 0.0, 0.0
+    per_r, n_em, cover, t_front, t_em = [], [], [], 0.0, 0.0
     for r in range(R):
         evd = L.events_to_device(parts[r], dev)
         mask, info = binned_boundary(L, torch, np, gw, mu_d, act, evd, torch.cuda.current_stream(dev))
@@ -400,32 +432,27 @@ def bench_study(args, L, torch, np, synth):
         n_em.append(info["n_emission"])
         cover.append(info["activity_pixels_inside"])
         ctx = L.Context(gw, mu_d, emission=mask)
+        evs = L.lmosem_events_load(ctx.handle, evd)
+        img = torch.as_tensor(start[0], device=dev)
+        series = []
         torch.cuda.synchronize()
         t0 = time.time()
-        f = ctx.reconstruct(evd, 10).double()
+        for _ in range(10):
+            L.lmosem_iterate(ctx.handle, evs, 1, img)
+            series.append(img.clone())
         torch.cuda.synchronize()
         t_em += time.time() - t0
+        L.lmosem_events_free(evs)
         ctx.close()
-        bgm = float(f[bg_t].mean())
-        for k, m in masks.items():
-            ratios[k].append(float(f[m].mean()) / bgm)
-        fs = f * (float(truth[brain_t].mean()) / float(f[brain_t].mean()))
-        nrmse.append(float(((fs - truth)[brain_t] ** 2).sum().sqrt() / (truth[brain_t] ** 2).sum().sqrt()))
-    row = {"window_kev": [100.0, g["win_hi_kev"]], "model": "first-order scatter, list mode, estimate confined to "
-           "a binned OS-MLEM boundary (64 position bins, 4 iterations, 5% threshold, 1-pixel margin)",
-           "events_per_realisation": int(np.mean([len(p["angle"]) for p in parts])),
-           "nrmse_mean": float(np.mean(nrmse)), "nrmse_std": float(np.std(nrmse)),
-           "emission_pixels_mean": float(np.mean(n_em)), "support_pixels": int((mu > 0).sum()),
-           "activity_inside_min": float(np.min(cover)), "front_end_s_per_realisation": t_front / R,
-           "reconstruct_s_per_realisation": t_em / R}
-    for k, v in ratios.items():
-        row[f"{k}_ratio_mean"] = float(np.mean(v))
-        row[f"{k}_ratio_std"] = float(np.std(v))
-        row[f"{k}_ratio_bias_pct"] = 100.0 * (float(np.mean(v)) - 8.0) / 8.0
-    rows.append(row)
-    log(f"boundary: {np.mean(n_em):.0f} of {int((mu > 0).sum())} pixels, caudate {row['caudate_ratio_mean']:.2f} +- "
-        f"{row['caudate_ratio_std']:.2f}, putamen {row['putamen_ratio_mean']:.2f} +- {row['putamen_ratio_std']:.2f}, "
-        f"nrmse {row['nrmse_mean']:.3f}")
+        per_r.append(series)
+    by_iter = [torch.stack([per_r[r][t] for r in range(R)]) for t in range(10)]
+    report({"window_kev": [100.0, g["win_hi_kev"]], "model": "first-order scatter, list mode, estimate confined "
+            "to a binned OS-MLEM boundary (64 position bins, 4 iterations, 5% threshold, 1-pixel margin)",
+            "events_per_realisation": int(np.mean([len(p["angle"]) for p in parts])),
+            **score(by_iter, [len(p["angle"]) for p in parts], sens_whole),
+            "emission_pixels_mean": float(np.mean(n_em)), "support_pixels": int((mu > 0).sum()),
+            "activity_inside_min": float(np.min(cover)), "front_end_s_per_realisation": t_front / R,
+            "reconstruct_s_per_realisation": t_em / R})
     # ordered subsets against plain list-mode MLEM (Sec. 2.2 defines the
     # subsets; Sec. 4 reports close to a fourfold speed-up for 4 subsets):
     # realisation 0 over the whole window; every iterate's full-data
@@ -475,7 +502,7 @@ def bench_study(args, L, torch, np, synth):
         "steps": 10, "warmup": 0, "ms_per_step": t_recon / 60 * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (Monte-Carlo list-mode events from the analytic brain phantom)",
-        "config": {"workload": f"study: {R} realisations of brain64 (200k events each over 100-175 keV), "
+        "config": {"workload": f"study: {R} realisations of brain64 ({n_ev} events each over 100-175 keV), "
                                "windows [143,175], [120,175], [100,175] keV, first-order scatter vs primary only, "
                                "list mode and binned (64 position x 1/2/3 energy bins), list mode confined to a "
                                "binned-OS-MLEM boundary, 10 iterations x 8 subsets, "
@@ -507,6 +534,8 @@ def main():
     ap.add_argument("--emission-from-binned", action="store_true",
                     help="confine the estimate to a crude boundary from a binned OS-MLEM (64 position bins, "
                          "the whole window, 4 iterations, 5%% threshold, 1-pixel margin) before timing")
+    ap.add_argument("--study-events", type=int, default=0,
+                    help="events per realisation in the study (default: the workload's 200k)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
