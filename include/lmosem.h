@@ -234,7 +234,8 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
 /* Autotuner: times the forward projection of the set's largest subset for
  * 8, 16 and 32 events per tile, the backprojection for 128-1024 rows per
  * chunk, and one whole iteration launched kernel by kernel against one
- * replayed as a HIP graph; re-plans the set with the fastest choices and
+ * replayed as a HIP graph (iterations estimated above 50 ms are replayed
+ * without that comparison); re-plans the set with the fastest choices and
  * returns them (outputs may be NULL).  With LMOSEM_TUNE_CACHE=<file> in the
  * environment the choice is looked up in / appended to that file, keyed by
  * support and emission-set sizes, angles, subsets, realisations and subset size.  Results do
