@@ -10,8 +10,8 @@
 //   update       f_q <- f_q * b_q / sens_q  (Eq. 7)
 //
 // The forward kernel is the hot loop.  A workgroup owns one tile of up to EV
-// events of one angle, sorted by detector position, and 256 emission pixels
-// (one per lane).  For every path end in the tile's rank range it reads the
+// events of one angle, sorted by detector position, and up to 256 emission
+// pixels (one per lane).  For every path end in the tile's rank range it reads the
 // (alpha, beta) pair of each lane's path once and reuses it for all EV
 // events; per event the term is one FMA for the exponent, one exp2 and one
 // FMA into the accumulator.  The event factor
@@ -29,12 +29,6 @@
 namespace lmo {
 
 constexpr int kRch = 128;   // path-end ranks staged in LDS per pass
-
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // Wave sum with DPP row operations (no LDS traffic): exchanges within quads
 // (lanes xor 1, xor 2), then mirrors within half-rows and rows give every
