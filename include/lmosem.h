@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define LMOSEM_ABI_VERSION 1u
+#define LMOSEM_ABI_VERSION 2u
 
 typedef enum {
     LMOSEM_OK = 0,
@@ -132,6 +132,9 @@ typedef struct {
     double backproject_ms;
     int64_t update_launches;    /* mean + update kernels of a sub-iteration */
     double update_ms;
+    int64_t network_launches;   /* learned-scatter contexts: launches of the fused network */
+    double network_ms;          /*   kernel, their summed time, */
+    int64_t network_pairs;      /*   and the (event, pixel) pairs they evaluated */
 } lmosem_stats;
 
 /* Version of this ABI (LMOSEM_ABI_VERSION of the built library). */

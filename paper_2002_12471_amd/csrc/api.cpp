@@ -41,8 +41,9 @@ struct lmosem_ctx {
     bool timing = false;
     struct Pending { hipEvent_t a, b; int kind; };
     std::vector<Pending> pending;
-    int64_t launches[3] = {0, 0, 0};
-    double ms[3] = {0.0, 0.0, 0.0};
+    int64_t launches[4] = {0, 0, 0, 0};
+    double ms[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t net_pairs = 0;     // pairs of the timed network launches
 };
 
 // Workspace of one prepared event set.
@@ -218,7 +219,8 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
 }
 
 // Run one launch, bracketed by HIP events on the context stream when timing
-// is enabled (kind 0 forward, 1 backprojection, 2 mean/update).
+// is enabled (kind 0 forward, 1 backprojection, 2 mean/update, 3 the network
+// of the learned-scatter rows).
 template <class F>
 hipError_t timed(lmosem_ctx *c, int kind, F &&launch, hipStream_t st) {
     if (!c->timing) return launch();
@@ -254,9 +256,20 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStre
     const Geo &g = c->g;
     const EvSet &v = s->s;
     const int rows = v.row_off[i + 1] - v.row_off[i];
-    if (c->surrogate)
+    if (c->surrogate) {
+        // with timing on, each network launch is timed on its own (its pair
+        // count is rows x emission pixels, split into batches of kPairCap)
+        const int64_t rows_per = std::max<int64_t>(1, kPairCap / g.n_q);
+        int64_t row0 = 0;
+        const LaunchWrap wrap = [&](const std::function<hipError_t()> &launch) {
+            c->net_pairs += std::min<int64_t>(rows_per, rows - row0) * g.n_q;
+            row0 += rows_per;
+            return timed(c, 3, launch, st);
+        };
         return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
-                              v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st);
+                              v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st,
+                              c->timing ? &wrap : nullptr);
+    }
     return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
                           v.efac, s->f, H, s->pmean, v.row_off[i], rows, st);
 }
@@ -1153,6 +1166,9 @@ lmosem_status lmosem_get_stats(const lmosem_ctx *c, lmosem_stats *out) {
     out->backproject_ms = c->ms[1];
     out->update_launches = c->launches[2];
     out->update_ms = c->ms[2];
+    out->network_launches = c->launches[3];
+    out->network_ms = c->ms[3];
+    out->network_pairs = c->net_pairs;
     return LMOSEM_OK;
 }
 
@@ -1162,7 +1178,8 @@ lmosem_status lmosem_set_timing(lmosem_ctx *c, int32_t enable) {
     if (e != hipSuccess) return dev_err(c, "timing", e);
     c->timing = enable != 0;
     if (c->timing) {
-        for (int k = 0; k < 3; ++k) { c->launches[k] = 0; c->ms[k] = 0.0; }
+        for (int k = 0; k < 4; ++k) { c->launches[k] = 0; c->ms[k] = 0.0; }
+        c->net_pairs = 0;
     }
     return LMOSEM_OK;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -155,10 +156,12 @@ hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, floa
 hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel, const int32_t *angle,
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st);
+// wraps one launch (per-kernel timing); the argument enqueues it
+using LaunchWrap = std::function<hipError_t(const std::function<hipError_t()> &)>;
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
                           int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X, float *y,
-                          int64_t pair_cap, hipStream_t st);
+                          int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net = nullptr);
 
 // ---- ALU rate probes (probe.hip) ----
 hipError_t measure_alu_rates(hipStream_t st, double *out3);

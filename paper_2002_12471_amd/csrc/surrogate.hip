@@ -309,7 +309,7 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
                           int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X,
-                          float *y, int64_t pair_cap, hipStream_t st) {
+                          float *y, int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net) {
     if (rows <= 0) return hipSuccess;
     SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     float4 *col4 = reinterpret_cast<float4 *>(col);
@@ -328,7 +328,8 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
         hipLaunchKernelGGL(k_surr_near, dim3((unsigned)nr), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
                            ev_angle, su, se, efac, rr, row_base, j0, nr, H, near);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = net_forward(net, X, pairs, y, st)) != hipSuccess) return e;
+        auto run_net = [&]() { return net_forward(net, X, pairs, y, st); };
+        if ((e = wrap_net ? (*wrap_net)(run_net) : run_net()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, near,
                            y, H);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EDEVICE", -5: "ESTATE",
           -6: "ENOTSUP"}
@@ -60,7 +60,9 @@ class lmosem_stats(ctypes.Structure):
                 ("event_tile", ctypes.c_int32), ("n_emission", ctypes.c_int32),
                 ("forward_launches", ctypes.c_int64), ("forward_ms", ctypes.c_double),
                 ("backproject_launches", ctypes.c_int64), ("backproject_ms", ctypes.c_double),
-                ("update_launches", ctypes.c_int64), ("update_ms", ctypes.c_double)]
+                ("update_launches", ctypes.c_int64), ("update_ms", ctypes.c_double),
+                ("network_launches", ctypes.c_int64), ("network_ms", ctypes.c_double),
+                ("network_pairs", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p

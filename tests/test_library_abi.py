@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib_path):
 def test_abi_version_and_argument_checks_without_gpu(lib_path):
     lib = ctypes.CDLL(lib_path)
     lib.lmosem_abi_version.restype = ctypes.c_uint32
-    assert lib.lmosem_abi_version() == 1
+    assert lib.lmosem_abi_version() == 2
     # null arguments are rejected before any device call
     lib.lmosem_create.restype = ctypes.c_int
     out = ctypes.c_void_p()
