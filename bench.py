@@ -86,23 +86,14 @@ def profiled_traffic(event_tile, workload, cached=False):
 
 
 def binned_boundary(L, torch, np, g, mu_d, act, evd, stream, n_pos=64, n_iters=4, threshold=0.05, margin=1):
-    """Emission set from a crude binned OS-MLEM image (events binned over the
-    whole window), thresholded and widened on the GPU; returns the mask and a
-    summary (sizes, front-end time, share of the true activity it holds)."""
-    edges = [g["win_lo_kev"], g["win_hi_kev"]]
+    """Emission set from a crude binned OS-MLEM image (the package's
+    boundary module), with a summary: sizes, front-end time and the share of
+    the true activity it holds."""
+    from paper_2002_12471_amd.boundary import binned_boundary as boundary
     torch.cuda.synchronize()
     t0 = time.time()
-    full = L.Context(g, mu_d, stream)
-    try:
-        counts = torch.empty(g["n_angles"] * n_pos, device=mu_d.device)
-        L.lmosem_bin_events(full.handle, evd, n_pos, edges, counts)
-        crude = torch.empty_like(mu_d)
-        L.lmosem_binned_reconstruct(full.handle, n_pos, edges, counts, n_iters, crude)
-        mask = torch.empty_like(mu_d)
-        L.lmosem_emission_mask(full.handle, crude, threshold, margin, mask)
-        torch.cuda.synchronize()
-    finally:
-        full.close()
+    mask = boundary(g, mu_d, evd, n_pos, n_iters, threshold, margin, stream)
+    torch.cuda.synchronize()
     t_front = time.time() - t0
     mk = mask.cpu().numpy() > 0
     n_sup = int((mu_d.cpu().numpy() > 0).sum())

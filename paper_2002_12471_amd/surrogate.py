@@ -1,8 +1,9 @@
 """Training driver of the learned scatter surrogate (orchestration only).
 
 For each attenuation map the caller supplies, a learned-scatter context
-(scatter_model 2: line integrals, scatter-point factors and the near-field
-band, no full path table) is built and lmosem_surrogate_samples turns the
+(scatter_model 2; samples need only its line integrals and scatter-point
+factors, so it never builds a path table or band) is made and
+lmosem_surrogate_samples turns the
 caller's (pixel, angle, u_bin, energy) draws into network inputs and exact
 targets;
 the samples of all maps are shuffled with the caller's permutation and the

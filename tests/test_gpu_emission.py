@@ -121,7 +121,6 @@ def test_brain64_masked_equals_full_support_from_zero_start(dev, cache):
     act, mu = synth.phantom(w)
     ev = synth.workload_events(w)
     evd = L.events_to_device(ev, dev)
-    X, Y = np.meshgrid(np.arange(mu.shape[1]), np.arange(mu.shape[0]))
     hot = act > 0
     grown = hot.copy()
     for dj, di in ((0, 1), (0, -1), (1, 0), (-1, 0)):
@@ -129,17 +128,17 @@ def test_brain64_masked_equals_full_support_from_zero_start(dev, cache):
     mask = (grown & (mu > 0)).astype(np.float32)
     full = L.Context(g, torch.as_tensor(mu, device=dev))
     try:
-        ref = _run_set(L, full, evd, mask, 3, cache=cache, tune=True)[None]
+        ref = _run_set(L, full, evd, mask, 3, cache=cache, tune=True)
     finally:
         full.close()
     em = L.Context(g, torch.as_tensor(mu, device=dev), emission=torch.as_tensor(mask, device=dev))
     try:
         assert em.stats()["n_emission"] == int(mask.sum())
-        got = _run_set(L, em, evd, (mu > 0).astype(np.float32), 3, cache=cache, tune=True)[None]
+        got = _run_set(L, em, evd, (mu > 0).astype(np.float32), 3, cache=cache, tune=True)
     finally:
         em.close()
     on = mask.ravel() > 0
-    r, gg = ref[0].ravel(), got[0].ravel()
+    r, gg = ref.ravel(), got.ravel()
     assert np.all(r[~on] == 0) and np.all(gg[~on] == 0)
     a, b = r[on].astype(np.float64), gg[on]
     assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4
@@ -221,6 +220,10 @@ def test_binned_boundary_then_list_mode(tiny, dev):
         ctx.close()
     hot = (c >= 0.05 * c.max()) & (mu > 0)
     assert np.all(mk[hot] == 1) and np.all(mk[mu <= 0] == 0)
+    # the package's helper chains the same calls
+    from paper_2002_12471_amd.boundary import binned_boundary
+    helper = binned_boundary(g, torch.as_tensor(mu, device=dev), L.events_to_device(ev, dev), 16, 3, 0.05, 1)
+    np.testing.assert_array_equal(helper.cpu().numpy(), mk)
     hj, hi = np.nonzero(hot)
     for j, i in zip(*np.nonzero(mk)):
         assert np.min((hj - j) ** 2 + (hi - i) ** 2) <= 1
