@@ -45,6 +45,59 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     return v;
 }
 
+// Per-event wave sums of a tile, EV values per lane, by halving exchanges:
+// at each step a lane pairs with a partner that differs in one lane bit,
+// keeps half of its values (the upper half when that bit is set), and adds
+// the partner's copy of the half it kept.  The lane bits are taken in the
+// order 3, 2, 0, 1, 4, 5, whose partners are a row mirror, a half-row
+// mirror, two quad permutations (all DPP operands of the add) and shuffles
+// across rows; each pairing flips its bit and only bits not yet used, so the
+// two partners always hold the same events.  After log2(EV) halving steps a
+// lane holds one event, its index read from the used bits (first one most
+// significant); plain sums over the remaining bits finish the wave total.
+template <int B>
+__device__ __forceinline__ float partner(float v) {
+    if constexpr (B == 3) return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+    else if constexpr (B == 2) return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    else if constexpr (B == 0) return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    else if constexpr (B == 1) return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    else return __shfl_xor(v, 1 << B, 64);
+}
+
+constexpr int kSumBits[6] = {3, 2, 0, 1, 4, 5};
+
+template <int S, int N, int EV>
+__device__ __forceinline__ void halve_events(float (&v)[EV], int lane, int &e) {
+    if constexpr (S < 6) {
+        constexpr int B = kSumBits[S];
+        if constexpr (N > 1) {
+            const bool up = (lane >> B) & 1;
+#pragma unroll
+            for (int i = 0; i < N / 2; ++i) {
+                const float send = up ? v[i] : v[i + N / 2];
+                const float keep = up ? v[i + N / 2] : v[i];
+                v[i] = keep + partner<B>(send);
+            }
+            e = 2 * e + (up ? 1 : 0);
+            halve_events<S + 1, N / 2, EV>(v, lane, e);
+        } else {
+            v[0] += partner<B>(v[0]);
+            halve_events<S + 1, 1, EV>(v, lane, e);
+        }
+    }
+}
+
+// the writer lanes: every bit not used for halving is 0
+template <int EV>
+constexpr int writer_mask() {
+    int m = 0, n = EV;
+    for (int s = 0; s < 6; ++s) {
+        if (n > 1) n /= 2;
+        else m |= 1 << kSumBits[s];
+    }
+    return m;
+}
+
 // buffer resource word 3 of the gfx9 family (raw, untyped 32-bit access)
 constexpr int kBufferWord3 = 0x00020000;
 
@@ -113,20 +166,26 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
     const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
     const float edge = expf(-4.5f);
 
+    // the staging thread's event (fixed: the group width is a multiple of
+    // EV) with its position in FP64 (both positions are O(10 cm)) and its
+    // energy factor, read once per tile
+    const int e_st = tid & (EV - 1), r_st = tid / EV, r_step = gw / EV;
+    const bool e_ok = e_st < tl.n;
+    const double u_st = e_ok ? ((double)su[tl.e0 + e_st] - 0.5 * g.n_bins) * g.bin_cm : 0.0;
+    const float ef_st = e_ok ? efac[tl.e0 + e_st] : 0.0f;
     for (int rc = tl.r0; rc < tl.r1; rc += kRch) {
         const int nr = min(kRch, tl.r1 - rc);
         const int nr4 = (nr + 3) & ~3;      // ranks are processed in groups of 4
         __syncthreads();
-        for (int idx = tid; idx < nr4 * EV; idx += gw) {
-            const int r = idx / EV, e = idx - r * EV;
+        for (int r = r_st; r < nr4; r += r_step) {
             float kv = 0.0f;
-            if (e < tl.n && r < nr) {
-                // offset in FP64 (both positions are O(10 cm)), response in FP32
-                const float d = (float)(((double)su[tl.e0 + e] - 0.5 * g.n_bins) * g.bin_cm - us[rc + r]);
+            if (e_ok && r < nr) {
+                // offset in FP64, response in FP32
+                const float d = (float)(u_st - us[rc + r]);
                 const float gk = __expf(-d * d * inv2s2) - edge;
-                kv = gk > 0.0f ? gk * efac[tl.e0 + e] : 0.0f;
+                kv = gk > 0.0f ? gk * ef_st : 0.0f;
             }
-            Ks[idx] = kv;
+            Ks[r * EV + e_st] = kv;
         }
         __syncthreads();
         if (wave_on) {
@@ -160,10 +219,13 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
             if (e < tl.n) Hq[(size_t)e * g.n_qpad] = acc[e];
     }
     const float fq = (wave_on && q < g.n_q) ? f[(size_t)tl.real * g.n_qpad + q] : 0.0f;
+    {
+        float v[EV];
 #pragma unroll
-    for (int e = 0; e < EV; ++e) {
-        const float v = wave_sum_to_lane63(fq * acc[e]);
-        if (lane == 63) red[wave * EV + e] = v;
+        for (int e = 0; e < EV; ++e) v[e] = fq * acc[e];
+        int e = 0;
+        halve_events<0, EV, EV>(v, lane, e);
+        if ((lane & writer_mask<EV>()) == 0) red[wave * EV + e] = v[0];
     }
     __syncthreads();
     if (tid < tl.n) {
