@@ -235,6 +235,22 @@ hipError_t timed(lmosem_ctx *c, int kind, F &&launch, hipStream_t st) {
     return hipSuccess;
 }
 
+// As timed, for one kernel launched with its own start and end events
+// (launch receives them, or null when timing is off): the interval then
+// covers the kernel alone, as a profiler's kernel trace does.
+template <class F>
+hipError_t timed_kernel(lmosem_ctx *c, int kind, F &&launch) {
+    if (!c->timing) return launch(nullptr);
+    lmosem_ctx::Pending p{nullptr, nullptr, kind};
+    hipError_t e;
+    if ((e = hipEventCreate(&p.a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&p.b)) != hipSuccess) { hipEventDestroy(p.a); return e; }
+    const KernelEvents ke{p.a, p.b};
+    if ((e = launch(&ke)) != hipSuccess) { hipEventDestroy(p.a); hipEventDestroy(p.b); return e; }
+    c->pending.push_back(p);
+    return hipSuccess;
+}
+
 hipError_t drain_timing(lmosem_ctx *c) {
     hipError_t e = hipSuccess;
     for (auto &p : c->pending) {
@@ -270,8 +286,10 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStre
                               v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st,
                               c->timing ? &wrap : nullptr);
     }
-    return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u, v.e,
-                          v.efac, s->f, H, s->pmean, v.row_off[i], rows, st);
+    return timed_kernel(c, 0, [&](const KernelEvents *ke) {
+        return launch_forward(v.ev_tile, g, c->t, v.tiles + v.tile_off[i], v.tile_off[i + 1] - v.tile_off[i], v.u,
+                              v.e, v.efac, s->f, H, s->pmean, v.row_off[i], rows, st, ke);
+    });
 }
 
 int mean_groups(const lmosem_ctx *c) { return c->surrogate ? 1 : forward_groups(c->g); }
@@ -294,12 +312,14 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     hipError_t e;
     if (cached) {
         // event means and their inverses straight from the stored rows
-        if ((e = timed(c, 0, [&] {
-                 return launch_row_dot(g, rrange, v.n_real, rows, H, s->f, s->mean, s->inv, c->skipped_dev, st);
-             }, st)) != hipSuccess)
+        if ((e = timed_kernel(c, 0, [&](const KernelEvents *ke) {
+                 return launch_row_dot(g, rrange, v.n_real, rows, H, s->f, s->mean, s->inv, c->skipped_dev, st, ke);
+             })) != hipSuccess)
             return e;
-    } else if ((n_tiles > 0 || (c->surrogate && rows > 0)) &&
-               (e = timed(c, 0, [&] { return forward_rows(c, s, i, H, st); }, st)) != hipSuccess) {
+    } else if (c->surrogate && rows > 0) {
+        // many kernels per sub-iteration: bracketed as a whole
+        if ((e = timed(c, 0, [&] { return forward_rows(c, s, i, H, st); }, st)) != hipSuccess) return e;
+    } else if (n_tiles > 0 && (e = forward_rows(c, s, i, H, st)) != hipSuccess) {
         return e;
     }
     if (rows > 0 && !cached &&
@@ -309,9 +329,9 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, st)) != hipSuccess)
         return e;
     if (n_chunks > 0 &&
-        (e = timed(c, 1, [&] {
-             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, H, s->inv, s->pb, st);
-         }, st)) != hipSuccess)
+        (e = timed_kernel(c, 1, [&](const KernelEvents *ke) {
+             return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, H, s->inv, s->pb, st, ke);
+         })) != hipSuccess)
         return e;
     if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, st); }, st)) != hipSuccess)
         return e;

@@ -111,16 +111,24 @@ hipError_t launch_gather_counts(const float *counts, const int *row_bin, int n_r
 hipError_t launch_count_weights(const float *y, const float *inv, int n_rows, float *w, hipStream_t st);
 
 // ---- per sub-iteration kernels (osem.hip) ----
+// Events a launch function records at its kernel's start and end (HIP's
+// launch with events: the timestamps bracket the kernel itself, not the
+// queue work around it); a launch function that launches nothing records
+// both at once.
+struct KernelEvents {
+    hipEvent_t start, stop;
+};
 __host__ __device__ int forward_groups(const Geo &g);
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
                           const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
-                          float *pmean, int row_base, int n_rows, hipStream_t st);
+                          float *pmean, int row_base, int n_rows, hipStream_t st, const KernelEvents *ke = nullptr);
 hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean, float *inv,
                        unsigned long long *skipped, hipStream_t st);
 hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_rows, const float *H, const float *f,
-                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st);
+                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st,
+                          const KernelEvents *ke = nullptr);
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
-                              const float *inv, float *pb, hipStream_t st);
+                              const float *inv, float *pb, hipStream_t st, const KernelEvents *ke = nullptr);
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
                          const float *sens, float *f, hipStream_t st);
 hipError_t launch_loglik(const Geo &g, const int *rrange, int n_real, const float *mean,

@@ -19,6 +19,7 @@
 // is computed once per (event, path end) into LDS and read back as a
 // broadcast; the energy factor 2^(-c2 (E_j - e_c)^2) / Z_K is precomputed per
 // event at ingest.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -275,27 +276,43 @@ __global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__
 // pixel groups of the forward launch (one group per workgroup)
 __host__ __device__ int forward_groups(const Geo &g) { return (g.n_qpad + 64 * g.fwd_waves - 1) / (64 * g.fwd_waves); }
 
+// a launch, with the kernel's own start and end events when ke is given
+template <typename K, typename... A>
+static hipError_t launch(K kernel, dim3 grid, dim3 block, hipStream_t st, const KernelEvents *ke, A... args) {
+    if (ke)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ke->start, ke->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    return hipGetLastError();
+}
+
+// nothing to launch: the events still bracket an (empty) interval
+static hipError_t no_launch(const KernelEvents *ke, hipStream_t st) {
+    if (!ke) return hipSuccess;
+    hipError_t e = hipEventRecord(ke->start, st);
+    return e == hipSuccess ? hipEventRecord(ke->stop, st) : e;
+}
+
 template <int EV>
 static hipError_t launch_ev(const Geo &g, const Tables &t, const Tile *tiles, int n_tiles, const float *ev_u,
                             const float *ev_e, const float *efac, const float *f, float *H, float *pmean,
-                            int row_base, int n_rows, hipStream_t st) {
+                            int row_base, int n_rows, hipStream_t st, const KernelEvents *ke) {
     const int n_work = n_tiles * forward_groups(g);
-    hipLaunchKernelGGL(k_forward<EV>, dim3(n_work), dim3(64 * g.fwd_waves), 0, st, g, tiles, n_tiles, t.T, t.us_sorted, ev_u,
-                       ev_e, efac, f, H, pmean, row_base, n_rows);
-    return hipGetLastError();
+    return launch(k_forward<EV>, dim3(n_work), dim3(64 * g.fwd_waves), st, ke, g, tiles, n_tiles,
+                  (const float2 *)t.T, (const double *)t.us_sorted, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows);
 }
 
 hipError_t launch_forward(int ev_tile, const Geo &g, const Tables &t, const Tile *tiles, int n_tiles,
                           const float *ev_u, const float *ev_e, const float *efac, const float *f, float *H,
-                          float *pmean, int row_base, int n_rows, hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
+                          float *pmean, int row_base, int n_rows, hipStream_t st, const KernelEvents *ke) {
+    if (n_tiles <= 0) return no_launch(ke, st);
     switch (ev_tile) {
     case 16:
-        return launch_ev<16>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
+        return launch_ev<16>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st, ke);
     case 32:
-        return launch_ev<32>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
+        return launch_ev<32>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st, ke);
     default:
-        return launch_ev<8>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st);
+        return launch_ev<8>(g, t, tiles, n_tiles, ev_u, ev_e, efac, f, H, pmean, row_base, n_rows, st, ke);
     }
 }
 
@@ -361,18 +378,14 @@ __global__ __launch_bounds__(256) void k_row_dot(Geo g, const int *__restrict__ 
 }
 
 hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_rows, const float *H, const float *f,
-                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st) {
-    if (n_rows <= 0) return hipSuccess;
-    if (g.n_qpad / 4 <= 64) {   // rows of at most 256 floats: 16 lanes each
-        const int blocks = std::min((n_rows + 15) / 16, 16384);
-        hipLaunchKernelGGL(k_row_dot<16>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, mean, inv,
-                           skipped);
-    } else {
-        const int blocks = std::min((n_rows + 3) / 4, 16384);
-        hipLaunchKernelGGL(k_row_dot<64>, dim3(blocks), dim3(256), 0, st, g, rrange, n_real, n_rows, H, f, mean, inv,
-                           skipped);
-    }
-    return hipGetLastError();
+                          float *mean, float *inv, unsigned long long *skipped, hipStream_t st,
+                          const KernelEvents *ke) {
+    if (n_rows <= 0) return no_launch(ke, st);
+    if (g.n_qpad / 4 <= 64)   // rows of at most 256 floats: 16 lanes each
+        return launch(k_row_dot<16>, dim3(std::min((n_rows + 15) / 16, 16384)), dim3(256), st, ke, g, rrange, n_real,
+                      n_rows, H, f, mean, inv, skipped);
+    return launch(k_row_dot<64>, dim3(std::min((n_rows + 3) / 4, 16384)), dim3(256), st, ke, g, rrange, n_real, n_rows,
+                  H, f, mean, inv, skipped);
 }
 
 // pb[c][q] = sum_{j in chunk c} H[j][q] inv[j]; four columns per thread.
@@ -399,11 +412,10 @@ __global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restr
 }
 
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
-                              const float *inv, float *pb, hipStream_t st) {
-    if (n_chunks <= 0) return hipSuccess;
+                              const float *inv, float *pb, hipStream_t st, const KernelEvents *ke) {
+    if (n_chunks <= 0) return no_launch(ke, st);
     dim3 grid((unsigned)((g.n_qpad / 4 + 255) / 256), (unsigned)n_chunks);
-    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, st, g, chunks, H, inv, pb);
-    return hipGetLastError();
+    return launch(k_backproject, grid, dim3(256), st, ke, g, chunks, H, inv, pb);
 }
 
 // f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks:
