@@ -344,28 +344,63 @@ hipError_t launch_mean(const float *pmean, int n_groups, int n_rows, float *mean
 // mean[j] = sum_q f[real(j)][q] H[j][q] over whole padded rows (padding is zero
 // in both) and its inverse (0, and counted, when the mean is not positive).
 // LPR lanes per row (64, or 16 for short rows so that a wave takes four rows
-// at once), float4 loads and a butterfly sum; bound by reading H.
+// at once), float4 loads and a butterfly sum; bound by reading H.  Each lane
+// issues a batch of row loads (4 for short rows, which is all of them, 8
+// otherwise) before the first multiply, so a wave has a whole brain-sized
+// row in flight instead of one float4 per round trip; loads past the row end
+// are zeroed.  The row's realisation is looked up in offsets staged in LDS;
+// a short row's loads are issued before the lookup, so it hides under them
+// (a batch of many short realisations has a lookup per few hundred bytes).
+constexpr int kRowRealLds = 1024;   // realisation offsets kept in LDS (more: read from memory)
+
+template <int N>
+__device__ __forceinline__ void row_batch(const float4 *h, int k0, int step, int n4, float4 (&x)[N]) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int k = k0 + u * step;
+        const float4 v = h[min(k, n4 - 1)];
+        x[u] = k < n4 ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
 template <int LPR>
 __global__ __launch_bounds__(256) void k_row_dot(Geo g, const int *__restrict__ rrange, int n_real, int n_rows,
                                                  const float *__restrict__ H, const float *__restrict__ f,
                                                  float *__restrict__ mean, float *__restrict__ inv,
                                                  unsigned long long *__restrict__ skipped) {
     constexpr int kRowsPerBlock = 256 / LPR;
+    constexpr int kLoads = LPR == 16 ? 4 : 8;
+    __shared__ int rr_s[kRowRealLds + 1];
+    const bool rr_in_lds = n_real <= kRowRealLds;
+    if (rr_in_lds)
+        for (int i = threadIdx.x; i <= n_real; i += 256) rr_s[i] = rrange[i];
+    __syncthreads();
+    const int *rr = rr_in_lds ? rr_s : rrange;
     const int sub = threadIdx.x % LPR;
     const int n4 = g.n_qpad / 4;
     for (int j = blockIdx.x * kRowsPerBlock + threadIdx.x / LPR; j < n_rows; j += gridDim.x * kRowsPerBlock) {
-        int lo = 0, hi = n_real;   // realisation r with rrange[r] <= j < rrange[r+1]
-        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (rrange[m] <= j) lo = m; else hi = m; }
         const float4 *h = reinterpret_cast<const float4 *>(H + (size_t)j * g.n_qpad);
+        float4 x[kLoads];
+        // short rows: the whole row is one batch, issued before the lookup
+        if constexpr (LPR == 16) row_batch(h, sub, LPR, n4, x);
+        int lo = 0, hi = n_real;   // realisation r with rrange[r] <= j < rrange[r+1]
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (rr[m] <= j) lo = m; else hi = m; }
         const float4 *fr = reinterpret_cast<const float4 *>(f + (size_t)lo * g.n_qpad);
-        float s = 0.0f;
-        for (int k = sub; k < n4; k += LPR) {
-            const float4 x = h[k], y = fr[k];
-            s = fmaf(x.x, y.x, s);
-            s = fmaf(x.y, y.y, s);
-            s = fmaf(x.z, y.z, s);
-            s = fmaf(x.w, y.w, s);
+        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = sub; k0 < n4; k0 += kLoads * LPR) {
+            if (LPR != 16 || k0 != sub) row_batch(h, k0, LPR, n4, x);   // (short rows take one pass)
+            float4 y[kLoads];
+            row_batch(fr, k0, LPR, n4, y);
+#pragma unroll
+            for (int u = 0; u < kLoads; ++u) {
+                float &a = s4[u & 3];
+                a = fmaf(x[u].x, y[u].x, a);
+                a = fmaf(x[u].y, y[u].y, a);
+                a = fmaf(x[u].z, y[u].z, a);
+                a = fmaf(x[u].w, y[u].w, a);
+            }
         }
+        float s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
 #pragma unroll
         for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
         if (sub == 0) {
