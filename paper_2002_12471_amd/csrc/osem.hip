@@ -31,21 +31,6 @@ namespace lmo {
 
 constexpr int kRch = 128;   // path-end ranks staged in LDS per pass
 
-// Wave sum with DPP row operations (no LDS traffic): exchanges within quads
-// (lanes xor 1, xor 2), then mirrors within half-rows and rows give every
-// lane its 16-lane row sum, row 15 broadcasts add row 0 into row 1 and row 2
-// into row 3, and a lane-31 broadcast adds rows 0-1 into rows 2-3.  The total
-// is in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
-    return v;
-}
-
 // Per-event wave sums of a tile, EV values per lane, by halving exchanges:
 // at each step a lane pairs with a partner that differs in one lane bit,
 // keeps half of its values (the upper half when that bit is set), and adds

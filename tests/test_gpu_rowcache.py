@@ -116,6 +116,31 @@ def test_cached_rows_batched_realisations(dev):
         assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4, r
 
 
+def test_cached_rows_many_realisations(dev):
+    """More realisations (1100, two of them empty) than the row kernel keeps
+    offsets for in LDS, so it looks each row's realisation up in memory:
+    cached rows against the recomputing path."""
+    L = _lib()
+    w = synth.workload("tiny")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    sizes = np.random.default_rng(5).integers(1, 40, size=1100)
+    sizes[[3, 500]] = 0
+    ev = synth.workload_events(w, n_events=int(sizes.sum()))
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+    ctx = L.Context(dict(g, n_subsets=4), torch.as_tensor(mu, device=dev))
+    try:
+        evd = L.events_to_device(ev, dev)
+        ref, _ = _iterate(L, ctx, evd, mu, 3, cache=False, offsets=offsets)
+        got, _ = _iterate(L, ctx, evd, mu, 3, cache=True, offsets=offsets, calls=3)
+    finally:
+        ctx.close()
+    sup = mu.ravel() > 0
+    a, b = ref.reshape(len(sizes), -1)[:, sup].astype(np.float64), got.reshape(len(sizes), -1)[:, sup]
+    assert np.all(np.isfinite(b))
+    assert np.max(np.abs(b - a) / np.maximum(a, 1e-3 * a.max())) <= 1e-4
+
+
 def test_cached_rows_learned_scatter(dev):
     """A learned-scatter context: rows from the network's path, cached after
     the first iteration, against recomputing them every iteration."""
