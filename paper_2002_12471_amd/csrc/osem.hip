@@ -95,12 +95,13 @@ __device__ __forceinline__ void load_group(__amdgpu_buffer_rsrc_t rs, uint32_t l
         v[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, row0 + i * rstride, 0));
 }
 
-// the terms of four ranks for all EV events: exponent FMA, exp2, accumulate
-template <int EV>
+// the terms of NR (of four loaded) ranks for all EV events: exponent FMA,
+// exp2, accumulate
+template <int EV, int NR = 4>
 __device__ __forceinline__ void term_group(const float2 (&v)[4], const float *Kg, const float (&et)[EV],
                                            float (&acc)[EV]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NR; ++i) {
         const float4 *kr = reinterpret_cast<const float4 *>(Kg + i * EV);
         float4 k4[EV / 4];
 #pragma unroll
@@ -116,6 +117,22 @@ __device__ __forceinline__ void term_group(const float2 (&v)[4], const float *Kg
             acc[4 * e4 + 1] = fmaf(k4[e4].y, x[4 * e4 + 1], acc[4 * e4 + 1]);
             acc[4 * e4 + 2] = fmaf(k4[e4].z, x[4 * e4 + 2], acc[4 * e4 + 2]);
             acc[4 * e4 + 3] = fmaf(k4[e4].w, x[4 * e4 + 3], acc[4 * e4 + 3]);
+        }
+    }
+}
+
+// the last group of a chunk, with its 1 to 4 ranks (a wave-uniform count):
+// rank by rank behind scalar branches
+template <int EV>
+__device__ __forceinline__ void term_tail(const float2 (&v)[4], const float *Kg, const float (&et)[EV],
+                                          float (&acc)[EV], int nr_last) {
+    const float2 v0[4] = {v[0], v[0], v[0], v[0]};
+    term_group<EV, 1>(v0, Kg, et, acc);
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        if (i < nr_last) {
+            const float2 vi[4] = {v[i], v[i], v[i], v[i]};
+            term_group<EV, 1>(vi, Kg + i * EV, et, acc);
         }
     }
 }
@@ -161,7 +178,7 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
     const float ef_st = e_ok ? efac[tl.e0 + e_st] : 0.0f;
     for (int rc = tl.r0; rc < tl.r1; rc += kRch) {
         const int nr = min(kRch, tl.r1 - rc);
-        const int nr4 = (nr + 3) & ~3;      // ranks are processed in groups of 4
+        const int nr4 = (nr + 3) & ~3;      // ranks rounded up to whole groups of 4 (K' = 0 past nr)
         __syncthreads();
         for (int r = r_st; r < nr4; r += r_step) {
             float kv = 0.0f;
@@ -176,25 +193,38 @@ __device__ __forceinline__ void forward_item(const Geo &g, const Tile *__restric
         __syncthreads();
         if (wave_on) {
             // groups of 4 ranks in two alternating register sets: the next
-            // group's entries are loaded while this one is computed.  Ranks
-            // past the tile (up to 7) read the padding rows of the table and
-            // meet K' = 0.
-            const int n_grp = __builtin_amdgcn_readfirstlane(nr4 >> 2);
+            // group's entries are loaded while this one is computed.  With 8
+            // events per tile the chunk's last group computes only its own 1
+            // to 4 ranks; with more (where the separate tail costs registers
+            // and waves) it runs whole, its padding ranks meeting K' = 0.
+            // Loads past the tile read padding rows of the table, unused.
+            constexpr bool kExactTail = EV == 8;
+            const int n_full = __builtin_amdgcn_readfirstlane(kExactTail ? (nr - 1) >> 2 : nr4 >> 2);
+            const int nr_last = __builtin_amdgcn_readfirstlane(nr - 4 * n_full);
             const uint64_t left = (uint64_t)(g.n_rpad - rc) * rstride;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float2 *>(Ta + (size_t)rc * g.n_qpad), (short)0,
                 (int)(uint32_t)std::min<uint64_t>(left, 0xFFFFFFFFull), kBufferWord3);
-            const uint32_t base = 0;
             float2 a[4], b[4];
-            load_group(rs, lane_off, base, rstride, a);
+            load_group(rs, lane_off, 0u, rstride, a);
             int gi = 0;
-            for (; gi + 1 < n_grp; gi += 2) {
-                load_group(rs, lane_off, base + (uint32_t)(gi + 1) * 4u * rstride, rstride, b);
+            for (; gi + 1 < n_full; gi += 2) {
+                load_group(rs, lane_off, (uint32_t)(gi + 1) * 4u * rstride, rstride, b);
                 term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
-                load_group(rs, lane_off, base + (uint32_t)(gi + 2) * 4u * rstride, rstride, a);
+                load_group(rs, lane_off, (uint32_t)(gi + 2) * 4u * rstride, rstride, a);
                 term_group<EV>(b, Ks + (gi + 1) * 4 * EV, et, acc);
             }
-            if (gi < n_grp) term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
+            if constexpr (kExactTail) {
+                if (gi < n_full) {   // one full group in a, then the last group
+                    load_group(rs, lane_off, (uint32_t)(gi + 1) * 4u * rstride, rstride, b);
+                    term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
+                    term_tail<EV>(b, Ks + (gi + 1) * 4 * EV, et, acc, nr_last);
+                } else {             // a holds the last group
+                    term_tail<EV>(a, Ks + gi * 4 * EV, et, acc, nr_last);
+                }
+            } else {
+                if (gi < n_full) term_group<EV>(a, Ks + gi * 4 * EV, et, acc);
+            }
         }
     }
 
