@@ -231,7 +231,9 @@ lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters
                              float *images_dev, double *loglik_host);
 
 /* Tuning: events per forward tile (8, 16 or 32; 0 restores the default 8)
- * for event sets loaded afterwards. */
+ * for event sets loaded afterwards.  A context starts from 8, or from
+ * LMOSEM_EVENT_TILE (8, 16 or 32) when that is set in the environment at
+ * creation; other values of it are ignored. */
 lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
 
 /* Autotuner: times the forward projection of the set's largest subset for
