@@ -310,6 +310,7 @@ def bench_study(args, L, torch, np, synth):
     realisations after every iteration), their ratios to the brain-background
     mean (truth 8) and the image NRMSE against the truth after scaling to the
     truth's brain mean."""
+    from paper_2002_12471_amd import tasks
     dev = torch.device("cuda:0")
     w = synth.workload("brain64")
     g = w.geom.as_dict()
@@ -321,47 +322,31 @@ def bench_study(args, L, torch, np, synth):
     caud, put = synth.striatal_masks(w.geom)
     brain = act > 0
     bg = brain & ~caud & ~put
-    masks = {k: torch.as_tensor(m & brain, device=dev) for k, m in (("caudate", caud), ("putamen", put))}
-    bg_t, brain_t = torch.as_tensor(bg, device=dev), torch.as_tensor(brain, device=dev)
-    truth = torch.as_tensor(act, device=dev).double()
+    masks = {"caudate": caud & brain, "putamen": put & brain}
+    truth = act.astype(np.float64)
     mu_d = torch.as_tensor(mu, device=dev)
     rows, events_done, t_recon = [], 0, 0.0
     start = np.broadcast_to((mu > 0).astype(np.float32), (R,) + mu.shape).copy()
 
     def score(by_iter, counts, sens_all):
-        """Task measures of one configuration from its images after each
-        iteration (by_iter[t][r] = image of realisation r after t + 1
-        iterations).  Uptake = mean activity in the region; its truth for
-        realisation r is the true region mean scaled so that the true image
-        predicts the realisation's counts (counts[r] = sum_q sens_q f_q, the
-        preset-count scale), and the normalised RMSE over realisations of the
-        uptake is reported per iteration (the paper's figure of merit).  At
-        the last iteration also the ratio of each region's mean to the brain
-        background mean (truth 8) and the image NRMSE after scaling to the
-        truth's brain mean."""
-        scale = float((sens_all * truth).sum())
+        """Task measures of one configuration (paper_2002_12471_amd.tasks)
+        from its images after each iteration (by_iter[t][r] = image of
+        realisation r after t + 1 iterations): each striatal region's uptake
+        NRMSE over the realisations after every iteration (the paper's figure
+        of merit), and after the last one each region's ratio to the brain
+        background mean (truth 8) and the image NRMSE."""
+        imgs = [x.double().cpu().numpy() for x in by_iter]
+        sens = sens_all.double().cpu().numpy()
         out = {}
         for k, m in masks.items():
-            u_true = float(truth[m].mean())
-            curve = []
-            for imgs in by_iter:
-                e = [float(imgs[r][m].double().mean()) / (counts[r] / scale * u_true) - 1.0 for r in range(R)]
-                curve.append(float(np.sqrt(np.mean(np.square(e)))))
-            out[f"{k}_uptake_nrmse_by_iter"] = curve
-        ratios = {k: [] for k in masks}
-        nrmse = []
-        for r in range(R):
-            f = by_iter[-1][r].double()
-            bgm = float(f[bg_t].mean())
-            for k, m in masks.items():
-                ratios[k].append(float(f[m].mean()) / bgm)
-            fs = f * (float(truth[brain_t].mean()) / float(f[brain_t].mean()))
-            nrmse.append(float(((fs - truth)[brain_t] ** 2).sum().sqrt() / (truth[brain_t] ** 2).sum().sqrt()))
-        out["nrmse_mean"], out["nrmse_std"] = float(np.mean(nrmse)), float(np.std(nrmse))
-        for k, v in ratios.items():
-            out[f"{k}_ratio_mean"] = float(np.mean(v))
-            out[f"{k}_ratio_std"] = float(np.std(v))
-            out[f"{k}_ratio_bias_pct"] = 100.0 * (float(np.mean(v)) - 8.0) / 8.0
+            out[f"{k}_uptake_nrmse_by_iter"] = [tasks.uptake_nrmse(im, m, truth, counts, sens) for im in imgs]
+        nrmse = tasks.image_nrmse(imgs[-1], truth, brain)
+        out["nrmse_mean"], out["nrmse_std"] = float(nrmse.mean()), float(nrmse.std())
+        for k, m in masks.items():
+            v = tasks.region_ratios(imgs[-1], m, bg)
+            out[f"{k}_ratio_mean"] = float(v.mean())
+            out[f"{k}_ratio_std"] = float(v.std())
+            out[f"{k}_ratio_bias_pct"] = 100.0 * (float(v.mean()) - 8.0) / 8.0
         return out
 
     def report(row):
