@@ -237,7 +237,7 @@ lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters
 lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
 
 /* Autotuner: times the forward projection of the set's largest subset for
- * 8, 16 and 32 events per tile, the backprojection for 128-1024 rows per
+ * 8, 16 and 32 events per tile, the backprojection for 64-1024 rows per
  * chunk, and one whole iteration launched kernel by kernel against one
  * replayed as a HIP graph (iterations estimated above 50 ms are replayed
  * without that comparison); re-plans the set with the fastest choices and

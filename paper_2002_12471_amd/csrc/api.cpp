@@ -1116,7 +1116,7 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
         }
         fwd_ms = best < 3.4e38f ? best : 0.0f;
         best = 3.4e38f;
-        for (int ch : {128, 256, 512, 1024}) {
+        for (int ch : {64, 128, 256, 512, 1024}) {
             if (e != hipSuccess) break;
             if ((e = plan_tiles(g, c->t, v, best_ev, ch, c->st, why)) != hipSuccess) break;
             lmosem_status ws = alloc_workspace(c, s);

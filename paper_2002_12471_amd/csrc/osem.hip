@@ -438,13 +438,14 @@ hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_row
                   H, f, mean, inv, skipped);
 }
 
-// pb[c][q] = sum_{j in chunk c} H[j][q] inv[j]; four columns per thread.
+// pb[c][q] = sum_{j in chunk c} H[j][q] inv[j]; four columns per thread,
+// blockDim.x threads per block along the row.
 __global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restrict__ chunks,
                                                      const float *__restrict__ H,
                                                      const float *__restrict__ inv,
                                                      float *__restrict__ pb) {
     const Chunk c = chunks[blockIdx.y];
-    const int q4 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    const int q4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (q4 >= g.n_qpad) return;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     const float *Hp = H + (size_t)c.j0 * g.n_qpad + q4;
@@ -464,8 +465,14 @@ __global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restr
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
                               const float *inv, float *pb, hipStream_t st, const KernelEvents *ke) {
     if (n_chunks <= 0) return no_launch(ke, st);
-    dim3 grid((unsigned)((g.n_qpad / 4 + 255) / 256), (unsigned)n_chunks);
-    return launch(k_backproject, grid, dim3(256), st, ke, g, chunks, H, inv, pb);
+    // the fewest blocks of up to 256 threads that cover the row's float4
+    // columns, each a whole number of waves with as few idle lanes as that
+    // allows (brain64's 368 columns: two blocks of 192 rather than 256 + 112)
+    const int n4 = g.n_qpad / 4;
+    const int nb = (n4 + 255) / 256;
+    const int bt = ((n4 + nb - 1) / nb + 63) / 64 * 64;
+    dim3 grid((unsigned)((n4 + bt - 1) / bt), (unsigned)n_chunks);
+    return launch(k_backproject, grid, dim3(bt), st, ke, g, chunks, H, inv, pb);
 }
 
 // f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks:
