@@ -237,8 +237,9 @@ lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters
 lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
 
 /* Autotuner: times the forward projection of the set's largest subset for
- * 8, 16 and 32 events per tile, the backprojection for 64-1024 rows per
- * chunk, and one whole iteration launched kernel by kernel against one
+ * 8, 16 and 32 events per tile, the backprojection with the update that
+ * adds its chunk partials for 64-1024 rows per chunk (using the set's
+ * scratch image), and one whole iteration launched kernel by kernel against one
  * replayed as a HIP graph (iterations estimated above 50 ms are replayed
  * without that comparison); re-plans the set with the fastest choices and
  * returns them (outputs may be NULL).  With LMOSEM_TUNE_CACHE=<file> in the

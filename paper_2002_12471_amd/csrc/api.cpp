@@ -1121,10 +1121,20 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
             if ((e = plan_tiles(g, c->t, v, best_ev, ch, c->st, why)) != hipSuccess) break;
             lmosem_status ws = alloc_workspace(c, s);
             if (ws != LMOSEM_OK) return ws;
+            // the backprojection together with the update that adds its chunk
+            // partials (more chunks: a faster backprojection, a longer update),
+            // five times over (on the set's scratch image)
             float ms = 0.0f;
             e = time_ms(c, [&] {
-                return launch_backproject(g, v.chunks + v.chunk_off[big], v.chunk_off[big + 1] - v.chunk_off[big],
-                                          s->H, s->inv, s->pb, c->st);
+                hipError_t r = hipSuccess;
+                for (int k = 0; k < 5 && r == hipSuccess; ++k) {
+                    r = launch_backproject(g, v.chunks + v.chunk_off[big], v.chunk_off[big + 1] - v.chunk_off[big],
+                                           s->H, s->inv, s->pb, c->st);
+                    if (r == hipSuccess)
+                        r = launch_update(g, v.crange + (size_t)big * (v.n_real + 1), v.n_real, s->pb,
+                                          c->t.sens + (size_t)big * g.n_qpad, s->f, c->st);
+                }
+                return r;
             }, ms);
             if (e == hipSuccess && ms < best) { best = ms; best_ch = ch; }
         }
