@@ -476,11 +476,16 @@ hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, c
 }
 
 // f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks:
-// 64 pixels per block, the chunks split over 4 waves (4 accumulators each)
-// and the wave partials added in a fixed order.
-__global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ crange, const float *__restrict__ pb,
-                                                const float *__restrict__ sens, float *__restrict__ f) {
-    __shared__ float part[4][64];
+// 64 pixels per block, the chunks split over kUpdWaves waves (4 accumulators
+// each, so a brain-sized subset's ~100 chunk partials take two rounds of
+// loads) and the wave partials added in a fixed order.
+constexpr int kUpdWaves = 16;
+
+__global__ __launch_bounds__(64 * kUpdWaves) void k_update(Geo g, const int *__restrict__ crange,
+                                                          const float *__restrict__ pb,
+                                                          const float *__restrict__ sens, float *__restrict__ f) {
+    constexpr int W = kUpdWaves;
+    __shared__ float part[W][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = blockIdx.x * 64 + lane;
     const int r = blockIdx.y;
@@ -488,18 +493,25 @@ __global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ c
     if (q < g.n_q) {
         const int c0 = crange[r], c1 = crange[r + 1];
         int c = c0 + wv;
-        for (; c + 12 < c1; c += 16) {
+        for (; c + 3 * W < c1; c += 4 * W) {
             a0 += pb[(size_t)c * g.n_qpad + q];
-            a1 += pb[(size_t)(c + 4) * g.n_qpad + q];
-            a2 += pb[(size_t)(c + 8) * g.n_qpad + q];
-            a3 += pb[(size_t)(c + 12) * g.n_qpad + q];
+            a1 += pb[(size_t)(c + W) * g.n_qpad + q];
+            a2 += pb[(size_t)(c + 2 * W) * g.n_qpad + q];
+            a3 += pb[(size_t)(c + 3 * W) * g.n_qpad + q];
         }
-        for (; c < c1; c += 4) a0 += pb[(size_t)c * g.n_qpad + q];
+        for (; c < c1; c += W) a0 += pb[(size_t)c * g.n_qpad + q];
     }
     part[wv][lane] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (wv == 0 && q < g.n_q) {
-        const float b = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        float b4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            b4[k] = 0.0f;
+#pragma unroll
+            for (int w = k; w < W; w += 4) b4[k] += part[w][lane];
+        }
+        const float b = (b4[0] + b4[1]) + (b4[2] + b4[3]);
         const float s = sens[q];
         float *fp = f + (size_t)r * g.n_qpad + q;
         if (s > 0.0f) *fp = (*fp * b) / s;
@@ -508,7 +520,8 @@ __global__ __launch_bounds__(256) void k_update(Geo g, const int *__restrict__ c
 
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
                          const float *sens, float *f, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3((g.n_q + 63) / 64, n_real), dim3(256), 0, st, g, crange, pb, sens, f);
+    hipLaunchKernelGGL(k_update, dim3((g.n_q + 63) / 64, n_real), dim3(64 * kUpdWaves), 0, st, g, crange, pb, sens,
+                       f);
     return hipGetLastError();
 }
 
