@@ -337,8 +337,16 @@ __global__ void k_mean(const float *__restrict__ pmean, int n_groups, int n_rows
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     int dead = 0;
     if (j < n_rows) {
+        // the partials in batches of 8 loads in flight, added in group order
         float s = 0.0f;
-        for (int k = 0; k < n_groups; ++k) s += pmean[(size_t)k * n_rows + j];
+        for (int k0 = 0; k0 < n_groups; k0 += 8) {
+            float p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = k0 + u < n_groups ? pmean[(size_t)(k0 + u) * n_rows + j] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < n_groups) s += p[u];
+        }
         mean[j] = s;
         dead = !(s > 1e-30f);
         inv[j] = dead ? 0.0f : 1.0f / s;
