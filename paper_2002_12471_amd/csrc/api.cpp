@@ -322,16 +322,23 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     } else if (n_tiles > 0 && (e = forward_rows(c, s, i, H, st)) != hipSuccess) {
         return e;
     }
-    if (rows > 0 && !cached &&
+    // computed rows: the event means are formed inside the backprojection
+    // (from the forward's pixel-group partials); cached rows come with them
+    const bool fused_means = !cached && v.chunk_rows <= kMaxChunkRows;
+    if (rows > 0 && !cached && !fused_means &&
         (e = timed(c, 2, [&] { return launch_mean(s->pmean, groups, rows, s->mean, s->inv, c->skipped_dev, st); }, st)) !=
             hipSuccess)
         return e;
-    if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, st)) != hipSuccess)
-        return e;
     if (n_chunks > 0 &&
         (e = timed_kernel(c, 1, [&](const KernelEvents *ke) {
+             if (fused_means)
+                 return launch_backproject_means(g, v.chunks + v.chunk_off[i], n_chunks, v.chunk_rows, H, s->pmean,
+                                                 groups, rows, s->mean, s->inv, c->skipped_dev, s->pb, st, ke);
              return launch_backproject(g, v.chunks + v.chunk_off[i], n_chunks, H, s->inv, s->pb, st, ke);
          })) != hipSuccess)
+        return e;
+    // the log-likelihood reads the means and the estimate before its update
+    if (want_ll && (e = launch_loglik(g, rrange, v.n_real, s->mean, s->f, sens, s->ll, st)) != hipSuccess)
         return e;
     if ((e = timed(c, 2, [&] { return launch_update(g, crange, v.n_real, s->pb, sens, s->f, st); }, st)) != hipSuccess)
         return e;

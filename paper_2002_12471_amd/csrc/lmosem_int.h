@@ -129,6 +129,16 @@ hipError_t launch_row_dot(const Geo &g, const int *rrange, int n_real, int n_row
                           const KernelEvents *ke = nullptr);
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
                               const float *inv, float *pb, hipStream_t st, const KernelEvents *ke = nullptr);
+// rows per backprojection chunk at most when the means are formed in the
+// backprojection (the autotuner's largest chunk)
+constexpr int kMaxChunkRows = 1024;
+// the event means and their inverses from the forward's pixel-group partials
+// (as launch_mean) and the backprojection, in one kernel; chunk_rows is the
+// plan's chunk size (at most kMaxChunkRows, else hipErrorInvalidValue)
+hipError_t launch_backproject_means(const Geo &g, const Chunk *chunks, int n_chunks, int chunk_rows,
+                                    const float *H, const float *pmean, int n_groups, int n_rows, float *mean,
+                                    float *inv, unsigned long long *skipped, float *pb, hipStream_t st,
+                                    const KernelEvents *ke = nullptr);
 hipError_t launch_update(const Geo &g, const int *crange, int n_real, const float *pb,
                          const float *sens, float *f, hipStream_t st);
 hipError_t launch_loglik(const Geo &g, const int *rrange, int n_real, const float *mean,

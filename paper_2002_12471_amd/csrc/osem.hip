@@ -470,17 +470,90 @@ __global__ __launch_bounds__(256) void k_backproject(Geo g, const Chunk *__restr
     *reinterpret_cast<float4 *>(pb + (size_t)blockIdx.y * g.n_qpad + q4) = acc;
 }
 
+// The backprojection with the event means formed first (the forward path,
+// so that no separate means kernel runs): each block adds its chunk's
+// pixel-group partials in group order, as k_mean does, into LDS; the first
+// column block also writes the means, their inverses and the dead-event
+// count; then the rows are weighted from LDS.
+__global__ __launch_bounds__(256) void k_backproject_means(Geo g, const Chunk *__restrict__ chunks,
+                                                           const float *__restrict__ H,
+                                                           const float *__restrict__ pmean, int n_groups,
+                                                           int n_rows, float *__restrict__ mean,
+                                                           float *__restrict__ inv,
+                                                           unsigned long long *__restrict__ skipped,
+                                                           float *__restrict__ pb) {
+    __shared__ float w_s[kMaxChunkRows];
+    const Chunk c = chunks[blockIdx.y];
+    const int n = c.j1 - c.j0;   // at most kMaxChunkRows (the plan's chunk size)
+    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+        const int i = i0 + threadIdx.x, j = c.j0 + i;
+        int dead = 0;
+        if (i < n) {
+            float s = 0.0f;
+            for (int k0 = 0; k0 < n_groups; k0 += 8) {
+                float p[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p[u] = k0 + u < n_groups ? pmean[(size_t)(k0 + u) * n_rows + j] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + u < n_groups) s += p[u];
+            }
+            dead = !(s > 1e-30f);
+            const float w = dead ? 0.0f : 1.0f / s;
+            w_s[i] = w;
+            if (blockIdx.x == 0) {
+                mean[j] = s;
+                inv[j] = w;
+            }
+        }
+        const unsigned long long m = __ballot(dead);
+        if (blockIdx.x == 0 && (threadIdx.x & 63) == 0 && m) atomicAdd(skipped, (unsigned long long)__popcll(m));
+    }
+    __syncthreads();
+    const int q4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (q4 >= g.n_qpad) return;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float *Hp = H + (size_t)c.j0 * g.n_qpad + q4;
+#pragma unroll 8
+    for (int i = 0; i < n; ++i) {
+        const float4 h = *reinterpret_cast<const float4 *>(Hp);
+        const float w = w_s[i];
+        acc.x = fmaf(h.x, w, acc.x);
+        acc.y = fmaf(h.y, w, acc.y);
+        acc.z = fmaf(h.z, w, acc.z);
+        acc.w = fmaf(h.w, w, acc.w);
+        Hp += g.n_qpad;
+    }
+    *reinterpret_cast<float4 *>(pb + (size_t)blockIdx.y * g.n_qpad + q4) = acc;
+}
+
+// the fewest blocks of up to 256 threads that cover the row's float4
+// columns, each a whole number of waves with as few idle lanes as that
+// allows (brain64's 368 columns: two blocks of 192 rather than 256 + 112)
+static dim3 backproject_block(const Geo &g) {
+    const int n4 = g.n_qpad / 4;
+    const int nb = (n4 + 255) / 256;
+    return dim3((unsigned)(((n4 + nb - 1) / nb + 63) / 64 * 64));
+}
+
 hipError_t launch_backproject(const Geo &g, const Chunk *chunks, int n_chunks, const float *H,
                               const float *inv, float *pb, hipStream_t st, const KernelEvents *ke) {
     if (n_chunks <= 0) return no_launch(ke, st);
-    // the fewest blocks of up to 256 threads that cover the row's float4
-    // columns, each a whole number of waves with as few idle lanes as that
-    // allows (brain64's 368 columns: two blocks of 192 rather than 256 + 112)
-    const int n4 = g.n_qpad / 4;
-    const int nb = (n4 + 255) / 256;
-    const int bt = ((n4 + nb - 1) / nb + 63) / 64 * 64;
-    dim3 grid((unsigned)((n4 + bt - 1) / bt), (unsigned)n_chunks);
-    return launch(k_backproject, grid, dim3(bt), st, ke, g, chunks, H, inv, pb);
+    const dim3 blk = backproject_block(g);
+    const dim3 grid((unsigned)((g.n_qpad / 4 + blk.x - 1) / blk.x), (unsigned)n_chunks);
+    return launch(k_backproject, grid, blk, st, ke, g, chunks, H, inv, pb);
+}
+
+hipError_t launch_backproject_means(const Geo &g, const Chunk *chunks, int n_chunks, int chunk_rows,
+                                    const float *H, const float *pmean, int n_groups, int n_rows, float *mean,
+                                    float *inv, unsigned long long *skipped, float *pb, hipStream_t st,
+                                    const KernelEvents *ke) {
+    if (chunk_rows > kMaxChunkRows) return hipErrorInvalidValue;
+    if (n_chunks <= 0) return no_launch(ke, st);
+    const dim3 blk = backproject_block(g);
+    const dim3 grid((unsigned)((g.n_qpad / 4 + blk.x - 1) / blk.x), (unsigned)n_chunks);
+    return launch(k_backproject_means, grid, blk, st, ke, g, chunks, H, pmean, n_groups, n_rows, mean, inv, skipped,
+                  pb);
 }
 
 // f[r][q] <- f[r][q] * b / sens with b summed over realisation r's chunks:
