@@ -425,7 +425,7 @@ def os_lm_mlem(H: np.ndarray, angle: np.ndarray, sens_subsets: np.ndarray, n_ite
         for i in range(n_subsets):
             Hi = H[rows[i]]
             f_new, mean, _skipped = subset_update(Hi, f, sens_subsets[i])
-            acc += float(np.sum(np.log(mean[mean > 0])) - np.dot(f, sens_subsets[i]))
+            acc += log_likelihood(mean, f, sens_subsets[i])
             f = f_new
         ll.append(acc)
     return f, np.array(ll)

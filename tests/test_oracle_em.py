@@ -1,5 +1,7 @@
 """Pins of the oracle's EM algebra (Eq. 6-9) by invariants that any correct
 list-mode OS-EM iterate satisfies."""
+import math
+
 import numpy as np
 import pytest
 
@@ -154,3 +156,27 @@ def test_binned_mlem_approaches_list_mode_em_as_bins_shrink():
         gaps.append(float(np.max(np.abs(f_b - f_lm)) / np.max(f_lm)))
     assert gaps[0] > gaps[1] > gaps[2], gaps
     assert gaps[2] < 0.25 * gaps[0] and gaps[2] < 0.02, gaps
+
+
+def test_log_likelihood_hand_values():
+    """Eq. 3 without its f-independent terms, on three events and two pixels
+    small enough to evaluate by hand: sum_j log(sum_q H_jq f_q) - sum_q f_q sens_q."""
+    H = np.array([[1.0, 2.0], [3.0, 4.0], [0.0, 5.0]])
+    f = np.array([1.0, 2.0])
+    sens = np.array([4.0, 11.0])
+    # means 5, 11, 10; expected count 1*4 + 2*11 = 26
+    assert O.log_likelihood(H @ f, f, sens) == pytest.approx(math.log(550.0) - 26.0, rel=1e-15)
+
+
+def test_os_lm_mlem_log_likelihood_and_iterate_by_hand():
+    """Two subsets (angles 0, 1, 0 with N_s = 2), one iteration, evaluated by
+    hand.  Subset 0 (events 0 and 2) from f = (1, 2): means 5 and 10, its
+    term log 50 - f.sens0 = log 50 - 2.5, backprojection (0.2, 0.9), new
+    f = (0.4, 1.8).  Subset 1 (event 1) from there: mean 8.4, term
+    log 8.4 - 3.7, new f = (0.4 * (3/8.4) / 0.25, 1.8 * (4/8.4) / 2)."""
+    H = np.array([[1.0, 2.0], [3.0, 4.0], [0.0, 5.0]])
+    angle = np.array([0, 1, 0])
+    sens = np.array([[0.5, 1.0], [0.25, 2.0]])
+    f, ll = O.os_lm_mlem(H, angle, sens, 1, np.array([1.0, 2.0]), 2)
+    assert ll[0] == pytest.approx(math.log(50.0) - 2.5 + math.log(8.4) - 3.7, rel=1e-14)
+    np.testing.assert_allclose(f, [0.4 * (3 / 8.4) / 0.25, 1.8 * (4 / 8.4) / 2.0], rtol=1e-14)
