@@ -1,7 +1,10 @@
 """GPU tests of the learned scatter surrogate: the bf16 MFMA network against
-the FP64 reference with the same bf16 rounding points, Adam, the training
-samples against the oracle's exact scatter sum, and an end-to-end training
-run that must beat primary-only compensation."""
+the FP64 reference with the same bf16 rounding points (outputs, every
+gradient entry, Adam), the training samples against the oracle's exact
+scatter sum, the near field exact, the assembled learned-scatter rows against
+the oracle's composition of the same rows, and the network trained as the
+surrogate workload is, whose event means must stay within 1 % of the exact
+path and of the oracle."""
 import numpy as np
 import pytest
 
@@ -86,9 +89,20 @@ def test_network_gradient_matches_reference(dev, count):
         L.lmosem_net_destroy(net)
     _, cache = M.forward(p, X, bf16_round=True)
     ref = M.backward(p, cache, dy, bf16_round=True)
+    # element by element: every entry within 2e-3 of its array's largest
+    # magnitude, and every entry above a tenth of that within 1 % of itself
+    # (the two sides round the layer deltas to bf16 at the same points and
+    # differ in FP32 against FP64 sums, and in the rare rounding tie a
+    # delta's last bf16 bit; measured at most 5.5e-4 and 3.4e-3)
     for k in ref:
-        err = np.linalg.norm(g[k].ravel() - ref[k].ravel()) / max(np.linalg.norm(ref[k]), 1e-12)
-        assert err <= 1e-2, (k, err)
+        r, gk = ref[k].ravel(), g[k].ravel().astype(np.float64)
+        scale = max(float(np.max(np.abs(r))), 1e-30)
+        err = np.abs(gk - r)
+        big = np.abs(r) >= 0.1 * scale
+        print(f"{k}: max |g - r| / max|r| = {err.max() / scale:.2e}, "
+              f"max rel on large entries = {np.max(err[big] / np.abs(r[big])) if big.any() else 0:.2e}")
+        assert np.all(err <= 2e-3 * scale), (k, float(err.max() / scale))
+        assert np.all(err[big] <= 1e-2 * np.abs(r[big])), k
 
 
 def test_adam_step_matches_reference(dev):
@@ -255,55 +269,131 @@ def test_surrogate_rows_do_not_depend_on_batching(dev):
         L.lmosem_net_destroy(net)
 
 
-def train_surrogate(L, dev, n_maps=48, per_map=8192, epochs=30, seed=404):
-    """Samples from random elliptical maps on the tiny grid, then Adam."""
-    w = synth.workload("surrogate_maps")
-    g = w.geom.as_dict()
-    rng = np.random.default_rng(seed)
-    Xs, ts = [], []
-    for _ in range(n_maps):
-        mu = synth.random_ellipse_map(w.geom, rng)
-        ctx = L.Context(g, torch.as_tensor(mu, device=dev))
-        s = synth.surrogate_sample_inputs(w.geom, mu, per_map, rng)
-        X, t = L.lmosem_surrogate_samples(ctx.handle, *[torch.as_tensor(s[k], device=dev)
-                                                        for k in ("pixel", "angle", "u_bin", "energy")])
-        Xs.append(X)
-        ts.append(t)
-        ctx.close()
-    X = torch.cat(Xs)
-    t = torch.cat(ts)
-    perm = torch.as_tensor(rng.permutation(X.shape[0]), device=dev)
-    X, t = X[perm].contiguous(), t[perm].contiguous()
-    net = L.lmosem_net_create(synth.mlp_init_params(seed))
-    loss = L.lmosem_net_train(net, X, t, batch=2048, epochs=epochs, lr=2e-3, lr_decay=0.92)
-    return net, loss
+def test_far_field_composition_matches_oracle(dev):
+    """A learned-scatter context with a fixed random network against the
+    oracle's composition of the same row (Eq. 8's denominator on the
+    surrogate path): for every emission pixel q of every event, the exact
+    primary plus first-order scatter sum where the event lies within q's own
+    position response (|u - u_q| < 3 sigma_u), and elsewhere
+    S0 max(exp(y) - 1e-4, 0) with y the FP64 reference network (bf16
+    rounding at the GPU's points) on the oracle's input features.
 
-
-def test_trained_surrogate_beats_primary_only(dev):
+    Tolerance per event: 1e-4 of the exact part plus 2e-3 max(1, |y|) of each
+    far pair's term, the reference network's bound (the network test above)
+    carried through exp; and, sharper, 2e-4 relative (a rounding tie that
+    moves one activation by one bf16 step changes one pair's output by about
+    1e-3, spread over the roughly 90 far pairs of an event; measured 3e-6)."""
     L = _lib()
-    net, loss = train_surrogate(L, dev)
+    w = synth.workload("tiny")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    ev = synth.workload_events(w, realisation=31, n_events=96)
+    p = _params(21)
+    net = L.lmosem_net_create(p)
     try:
-        assert loss[-1] < 0.2 * loss[0]
-        w = synth.workload("tiny")
-        g = w.geom.as_dict()
-        act, mu = synth.phantom(w)
-        ev = L.events_to_device(synth.workload_events(w), dev)
-        img = torch.as_tensor(act, device=dev)
-        mu_d = torch.as_tensor(mu, device=dev)
-        exact = L.Context(g, mu_d).forward(ev, img).double()
-        prim = L.Context(dict(g, scatter_model=0), mu_d).forward(ev, img).double()
-        sctx = L.Context(dict(g, scatter_model=2), mu_d)
-        L.lmosem_set_surrogate(sctx.handle, net)
-        surr = sctx.forward(ev, img).double()
-        err_s = float(((surr - exact).abs() / exact).mean())
-        err_p = float(((prim - exact).abs() / exact).mean())
-        print(f"mean relative event error: surrogate {err_s:.4f}, primary only {err_p:.4f}")
-        assert err_s < err_p / 3
-        # the surrogate context stores only the near-field band of the path table
-        ectx = L.Context(g, mu_d)
-        sctx.sensitivity(-1), ectx.sensitivity(-1)   # both build their list-mode tables
-        assert sctx.stats()["table_bytes"] < ectx.stats()["table_bytes"] / 2
-        ectx.close()
-        sctx.close()
+        ctx = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev))
+        L.lmosem_set_surrogate(ctx.handle, net)
+        got = ctx.forward(L.events_to_device(ev, dev), torch.as_tensor(act, device=dev)).double().cpu().numpy()
+        ctx.close()
     finally:
         L.lmosem_net_destroy(net)
+    m1 = O.OracleModel(g, mu)
+    n, dx = int(g["nx"]), float(g["pixel_cm"])
+    sig_u = float(g["fwhm_u_cm"]) / (2 * np.sqrt(2 * np.log(2)))
+    sig_e = float(g["fwhm_e_kev"]) / (2 * np.sqrt(2 * np.log(2)))
+    s0 = 1.0 / (dx * sig_e)
+    idx = (np.arange(n) - (n - 1) / 2) * dx
+    sup = np.flatnonzero((mu.ravel() > 0) & (act.ravel() > 0))
+    exact = np.zeros(len(got))
+    far_feats, far_ev, far_f = [], [], []
+    for j in range(len(got)):
+        a, u, e = int(ev["angle"][j]), float(m1.u_cm(ev["u_bin"][j])), float(ev["energy"][j])
+        th = float(g.get("angle0_rad", 0.0)) + 2 * np.pi * a / int(g["n_angles"])
+        for pix in sup:
+            uq = -np.sin(th) * idx[pix % n] + np.cos(th) * idx[pix // n]
+            if abs(u - uq) < 3 * sig_u:
+                exact[j] += act.flat[pix] * m1.h(int(pix), a, u, e)
+            else:
+                far_feats.append(O.surrogate_features(m1, int(pix), a, u, e))
+                far_ev.append(j)
+                far_f.append(float(act.flat[pix]))
+    y, _ = M.forward(p, np.array(far_feats), bf16_round=True)
+    term = np.array(far_f) * s0 * np.maximum(np.exp(y) - 1e-4, 0.0)
+    far = np.bincount(far_ev, weights=term, minlength=len(got))
+    slack = np.bincount(far_ev, weights=2e-3 * np.maximum(1.0, np.abs(y)) * term, minlength=len(got))
+    ref = exact + far
+    err = np.abs(got - ref)
+    bound = 1e-4 * exact + slack
+    print(f"{len(far_ev)} far pairs; far share of the means {float(np.mean(far / ref)):.2f}; "
+          f"max rel err {float(np.max(err / ref)):.2e}; max err / bound {float(np.max(err / bound)):.3f}")
+    assert np.all(far > 0) and np.all(exact > 0)
+    assert np.all(err <= bound)
+    assert np.all(err <= 2e-4 * ref)
+
+
+def _train_c4(L, dev):
+    """The learned scatter term trained as the surrogate workload is: 256
+    random elliptical maps on the 16x16 grid (the last 32 held out), 15,625
+    far-field samples each, 40 epochs of Adam on minibatches of 4096 by the
+    library's own kernels."""
+    from paper_2002_12471_amd import surrogate as S
+    wm = synth.workload("surrogate_maps")
+    gm = wm.geom.as_dict()
+    rng = np.random.default_rng(synth.seed_for(wm))
+    n_maps, per_map = wm.extra["n_maps"], wm.extra["n_samples"] // wm.extra["n_maps"]
+    maps = [synth.random_ellipse_map(wm.geom, rng, wm.extra.get("shell_prob", 0.0), wm.extra.get("body", (0.4, 0.9)))
+            for _ in range(n_maps)]
+    draws = [synth.surrogate_sample_inputs(wm.geom, m, per_map, rng) for m in maps]
+    X, t = S.make_samples(gm, maps[:-32], draws[:-32], dev)
+    Xv, tv = S.make_samples(gm, maps[-32:], draws[-32:], dev)
+    net, loss = S.train(synth.mlp_init_params(synth.seed_for(wm, 1)), X, t, rng.permutation(X.shape[0]),
+                        batch=4096, epochs=40, lr=2e-3, lr_decay=0.93)
+    return net, loss, S.mse(net, Xv, tv)
+
+
+@pytest.fixture(scope="module")
+def trained(dev):
+    L = _lib()
+    net, loss, heldout = _train_c4(L, dev)
+    yield net, loss, heldout
+    L.lmosem_net_destroy(net)
+
+
+def test_trained_surrogate_within_one_percent(dev, trained):
+    """The trained network inside the learned-scatter path on the tiny disk
+    (5,000 events at the true activity): mean relative event-mean error at
+    most 1 % against the exact FP32 path and against the FP64 oracle, and
+    the primary-only model (scatter ignored) at least ten times worse."""
+    L = _lib()
+    net, loss, heldout = trained
+    print(f"training loss {loss[0]:.4f} -> {loss[-1]:.4f}, held-out mse {heldout:.4f}")
+    assert loss[-1] < 0.2 * loss[0]
+    w = synth.workload("tiny")
+    g = w.geom.as_dict()
+    act, mu = synth.phantom(w)
+    ev_np = synth.workload_events(w)
+    ev = L.events_to_device(ev_np, dev)
+    img = torch.as_tensor(act, device=dev)
+    mu_d = torch.as_tensor(mu, device=dev)
+    ectx = L.Context(g, mu_d)
+    pctx = L.Context(dict(g, scatter_model=0), mu_d)
+    sctx = L.Context(dict(g, scatter_model=2), mu_d)
+    L.lmosem_set_surrogate(sctx.handle, net)
+    exact = ectx.forward(ev, img).double().cpu().numpy()
+    prim = pctx.forward(ev, img).double().cpu().numpy()
+    surr = sctx.forward(ev, img).double().cpu().numpy()
+    m = O.OracleModel(g, mu)
+    orc = m.system_matrix(ev_np) @ act.ravel()[m.support].astype(np.float64)
+    ok = orc > 0
+    err_s = float(np.mean(np.abs(surr[ok] - exact[ok]) / exact[ok]))
+    err_o = float(np.mean(np.abs(surr[ok] - orc[ok]) / orc[ok]))
+    err_p = float(np.mean(np.abs(prim[ok] - exact[ok]) / exact[ok]))
+    print(f"mean relative event error: surrogate vs exact {err_s:.4f}, vs oracle {err_o:.4f}; "
+          f"primary only {err_p:.4f}")
+    assert err_s <= 0.01 and err_o <= 0.01
+    assert err_p >= 10 * err_s
+    # the surrogate context stores only the near-field band of the path table
+    ectx.sensitivity(-1), sctx.sensitivity(-1)   # both build their list-mode tables
+    assert sctx.stats()["table_bytes"] < ectx.stats()["table_bytes"] / 2
+    for c in (ectx, pctx, sctx):
+        c.close()
