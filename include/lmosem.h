@@ -185,6 +185,25 @@ lmosem_status lmosem_sensitivity(lmosem_ctx *ctx, int32_t subset, float *sens_de
 lmosem_status lmosem_forward(lmosem_ctx *ctx, const lmosem_events *ev, const float *image_dev,
                              float *event_mean_dev);
 
+/* lmosem_forward for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same per-event means,
+ * bit for bit, with every buffer of the call (the estimate on the emission
+ * set, the sorted events and their tile plan, the sort's temporary storage,
+ * the system rows of one chunk of tiles at a time) carved from one
+ * file-scope device array of 64 MiB that the library holds on each GPU it
+ * runs on until the process ends.  No hipMalloc or hipFree, no allocating
+ * library routine.  Every call on a GPU shares that array (whatever its
+ * context), so calls that overlap on one GPU race; each call clears what
+ * must start at zero.  Needs the context's path tables (built by its first
+ * list-mode call, e.g. lmosem_sensitivity) and the exact path
+ * (scatter_model 0 or 1).  Validates the events and synchronises.
+ * Errors: EINVAL (arguments, or tables not built yet), ENOMEM (the events
+ * need more than the array holds: about 60 bytes per event plus a chunk of
+ * at least one tile of rows; roughly 1M events), ENOTSUP (scatter_model 2),
+ * ERANGE (events out of range). */
+lmosem_status lmosem_forward_noalloc(lmosem_ctx *ctx, const lmosem_events *ev, const float *image_dev,
+                                     float *event_mean_dev);
+
 /* Weighted backprojection b_q = sum_j h(q; A_j) w_j into image_dev [ny][nx]
  * (with w_j = 1/mean_j this is the numerator of Eq. 7 divided by f_q).
  * weights_dev [ev->n].  Validates the events (synchronises). */

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblmosem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["tables.hip", "events.hip", "osem.hip", "binned.hip", "emission.hip", "probe.hip", "mlp.hip", "surrogate.hip", "api.cpp"]
+SOURCES = ["tables.hip", "events.hip", "osem.hip", "binned.hip", "emission.hip", "probe.hip", "mlp.hip", "surrogate.hip", "noalloc.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

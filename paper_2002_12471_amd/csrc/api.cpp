@@ -694,6 +694,33 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
     return e == hipSuccess ? LMOSEM_OK : dev_err(c, "forward", e);
 }
 
+lmosem_status lmosem_forward_noalloc(lmosem_ctx *c, const lmosem_events *ev, const float *image_dev,
+                                     float *event_mean_dev) {
+    GUARD(c);
+    if (!c->paths_ready)
+        return set_err(c, LMOSEM_EINVAL, "the path tables are not built yet: make one list-mode call on this context "
+                                         "first (for example lmosem_sensitivity)");
+    if (c->surrogate) return set_err(c, LMOSEM_ENOTSUP, "no allocation-free forward for scatter_model 2");
+    if (!ev || ev->n < 0 || ev->n > 0x7fffffffLL || (ev->n > 0 && (!ev->angle || !ev->u_bin || !ev->energy_kev)))
+        return set_err(c, LMOSEM_EINVAL, "bad event arrays");
+    if (!image_dev || (ev->n > 0 && !event_mean_dev)) return set_err(c, LMOSEM_EINVAL, "bad arguments");
+    size_t need = 0;
+    hipError_t e = forward_noalloc_bytes(c->g, ev->n, c->ev_tile, need);
+    if (e != hipSuccess) return dev_err(c, "forward (no allocation)", e);
+    if (need > kScratchBytes)
+        return set_err(c, LMOSEM_ENOMEM, std::to_string(ev->n) + " events need " + std::to_string(need) +
+                                             " bytes of scratch memory; the library's scratch array holds " +
+                                             std::to_string(kScratchBytes));
+    lmosem_status st = LMOSEM_OK;
+    if (!check_events(c, ev, st)) return st;
+    int64_t terms = 0, useful = 0;
+    e = forward_noalloc(c->g, c->t, *ev, c->ev_tile, image_dev, event_mean_dev, c->skipped_dev, c->st, terms, useful);
+    if (e != hipSuccess) return dev_err(c, "forward (no allocation)", e);
+    c->terms += terms;
+    c->useful += useful;
+    return LMOSEM_OK;
+}
+
 lmosem_status lmosem_backproject(lmosem_ctx *c, const lmosem_events *ev, const float *weights_dev,
                                  float *image_dev) {
     GUARD(c);

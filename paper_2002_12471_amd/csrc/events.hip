@@ -122,6 +122,61 @@ __global__ void k_tile_ranks(Geo g, Tile *__restrict__ tiles, int n_tiles,
     useful[t] = use * g.n_q;
 }
 
+hipError_t launch_event_keys(const Geo &g, int64_t n, int n_real, const int64_t *offs_dev, const int32_t *angle,
+                             const float *u_bin, int force_subset, uint64_t *keys, int *idx, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, n, n_real, offs_dev, angle,
+                       u_bin, force_subset, keys, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_events(const Geo &g, int64_t n, const uint64_t *keys, const int *idx, const lmosem_events &ev,
+                                int *sa, float *su, float *se, float *efac, int *orig, int *counts, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_events, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, n, keys, idx,
+                       ev.u_bin, ev.energy_kev, ev.angle, sa, su, se, efac, orig, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranks(const Geo &g, Tile *tiles, int n_tiles, const double *us_sorted, const float *su,
+                             long long *terms, long long *useful, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_ranks, dim3((unsigned)((n_tiles + 127) / 128)), dim3(128), 0, st, g, tiles, n_tiles,
+                       us_sorted, su, terms, useful);
+    return hipGetLastError();
+}
+
+int sort_key_bits(int n_groups) {
+    int hi_bits = 1;
+    while ((1ll << hi_bits) < (long long)n_groups) ++hi_bits;
+    return 32 + hi_bits;
+}
+
+hipError_t sort_pairs_bytes(int64_t n, int n_groups, size_t &bytes) {
+    bytes = 0;
+    if (n <= 0) return hipSuccess;
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                              (const int *)nullptr, (int *)nullptr, (int)n, 0,
+                                              sort_key_bits(n_groups), (hipStream_t)nullptr);
+}
+
+hipError_t sort_pairs(void *tmp, size_t tmp_bytes, const uint64_t *keys, uint64_t *keys2, const int *idx, int *idx2,
+                      int64_t n, int n_groups, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys2, idx, idx2, (int)n, 0,
+                                              sort_key_bits(n_groups), st);
+}
+
+void host_tiles(const Geo &g, const std::vector<int> &counts, int n_angles_used, int ev_tile, std::vector<Tile> &tiles) {
+    tiles.clear();
+    int64_t pos = 0;
+    for (int a = 0; a < n_angles_used; ++a) {
+        const int c = counts[a];
+        for (int k = 0; k < c; k += ev_tile) tiles.push_back(Tile{(int)(pos + k), std::min(ev_tile, c - k), a, 0, 0, 0});
+        pos += c;
+    }
+}
+
 hipError_t sort_events(const Geo &g, const Tables &tb, const lmosem_events &ev,
                        const std::vector<int64_t> &offs, int force_subset, EvSet &set,
                        hipStream_t st, std::string &err) {

@@ -96,6 +96,33 @@ hipError_t sort_events(const Geo &g, const Tables &t, const lmosem_events &ev,
                        hipStream_t st, std::string &err);
 hipError_t plan_tiles(const Geo &g, const Tables &t, EvSet &set, int ev_tile, int chunk_rows,
                       hipStream_t st, std::string &err);
+// the steps of the ingest on buffers the caller provides (no allocation)
+hipError_t launch_event_keys(const Geo &g, int64_t n, int n_real, const int64_t *offs_dev, const int32_t *angle,
+                             const float *u_bin, int force_subset, uint64_t *keys, int *idx, hipStream_t st);
+hipError_t launch_gather_events(const Geo &g, int64_t n, const uint64_t *keys, const int *idx, const lmosem_events &ev,
+                                int *sa, float *su, float *se, float *efac, int *orig, int *counts, hipStream_t st);
+hipError_t launch_tile_ranks(const Geo &g, Tile *tiles, int n_tiles, const double *us_sorted, const float *su,
+                             long long *terms, long long *useful, hipStream_t st);
+int sort_key_bits(int n_groups);
+hipError_t sort_pairs_bytes(int64_t n, int n_groups, size_t &bytes);   // temporary storage of sort_pairs
+hipError_t sort_pairs(void *tmp, size_t tmp_bytes, const uint64_t *keys, uint64_t *keys2, const int *idx, int *idx2,
+                      int64_t n, int n_groups, hipStream_t st);
+// tiles of ev_tile consecutive events per angle of one sorted, single-subset,
+// single-realisation event set with counts[a] events at angle a
+void host_tiles(const Geo &g, const std::vector<int> &counts, int n_angles_used, int ev_tile, std::vector<Tile> &tiles);
+
+// ---- forward projection without allocation (noalloc.hip) ----
+// Bytes of the library's file-scope device scratch array, and its address on
+// the current device (looked up once per device).
+extern const size_t kScratchBytes;
+hipError_t scratch_address(void **ptr);
+// bytes of the scratch array that forward_noalloc needs for n events
+hipError_t forward_noalloc_bytes(const Geo &g, int64_t n, int ev_tile, size_t &need);
+// per-event means of the (validated) events at the image, in the caller's
+// event order, every buffer in the scratch array; synchronises st
+hipError_t forward_noalloc(const Geo &g, const Tables &t, const lmosem_events &ev, int ev_tile, const float *image,
+                           float *mean_out, unsigned long long *skipped, hipStream_t st, int64_t &terms,
+                           int64_t &useful);
 
 // ---- binned data (binned.hip) ----
 hipError_t launch_binned_rows(const Geo &g, const Tables &t, int n_pos, const double *edges_dev, int n_e,

@@ -75,6 +75,7 @@ _sigs = {
     "lmosem_last_error": (ctypes.c_char_p, [_P]),
     "lmosem_sensitivity": (_S, [_P, ctypes.c_int32, _P]),
     "lmosem_forward": (_S, [_P, ctypes.POINTER(lmosem_events), _P, _P]),
+    "lmosem_forward_noalloc": (_S, [_P, ctypes.POINTER(lmosem_events), _P, _P]),
     "lmosem_backproject": (_S, [_P, ctypes.POINTER(lmosem_events), _P, _P]),
     "lmosem_subset_update": (_S, [_P, ctypes.c_int32, ctypes.POINTER(lmosem_events), _P, _P]),
     "lmosem_reconstruct": (_S, [_P, ctypes.POINTER(lmosem_events), ctypes.POINTER(lmosem_batch),
@@ -202,6 +203,12 @@ def lmosem_forward(ctx, events: dict, image: torch.Tensor, mean_out: torch.Tenso
     ev = _events(events)
     _check(ctx, _lib.lmosem_forward(ctx, ctypes.byref(ev), _dev_ptr(image, torch.float32, "image"),
                                     _dev_ptr(mean_out, torch.float32, "mean")))
+
+
+def lmosem_forward_noalloc(ctx, events: dict, image: torch.Tensor, mean_out: torch.Tensor):
+    ev = _events(events)
+    _check(ctx, _lib.lmosem_forward_noalloc(ctx, ctypes.byref(ev), _dev_ptr(image, torch.float32, "image"),
+                                            _dev_ptr(mean_out, torch.float32, "mean")))
 
 
 def lmosem_backproject(ctx, events: dict, weights: torch.Tensor, image_out: torch.Tensor):
