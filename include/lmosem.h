@@ -64,7 +64,8 @@ typedef enum {
     LMOSEM_OK = 0,
     LMOSEM_EINVAL = -1,   /* bad argument or configuration */
     LMOSEM_ERANGE = -2,   /* input values outside their valid range */
-    LMOSEM_ENOMEM = -3,   /* device allocation failed or exceeds the context cap */
+    LMOSEM_ENOMEM = -3,   /* device allocation failed, or would exceed the context's
+                             memory cap (lmosem_set_memory_cap) */
     LMOSEM_EDEVICE = -4,  /* a HIP call failed; the context is poisoned */
     LMOSEM_ESTATE = -5,   /* context poisoned by an earlier device error */
     LMOSEM_ENOTSUP = -6   /* valid but not supported by this build */
@@ -267,6 +268,26 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
  * not depend on the choice beyond FP32 summation order.  Synchronises. */
 lmosem_status lmosem_autotune(lmosem_ctx *ctx, lmosem_evset *set, int32_t *event_tile,
                               int32_t *chunk_rows, int32_t *use_graphs);
+
+/* Cap on the device memory the context holds (0, the default: no cap): its
+ * tables plus the workspace, sorted events and row caches of its live event
+ * sets.  A call that would take the context past the cap returns
+ * LMOSEM_ENOMEM and leaves the context usable: the path tables are refused
+ * before they are allocated (for scatter_model 2, whose near-field band's
+ * width is known only once built, they are freed again), an event set after
+ * its sort is planned, a row cache before it is allocated.  Memory a call
+ * uses only while it runs is not counted.  Errors: EINVAL (bytes < 0). */
+lmosem_status lmosem_set_memory_cap(lmosem_ctx *ctx, int64_t bytes);
+/* The device bytes the context holds as the cap counts them. */
+lmosem_status lmosem_memory_held(const lmosem_ctx *ctx, int64_t *bytes);
+
+/* Testing hook for the error path: the context's next kernel launch of a
+ * list-mode call (forward projection, backprojection, update) is not made
+ * and reports a failed HIP launch instead, as a device failure would; that
+ * call returns LMOSEM_EDEVICE and poisons the context (every later call
+ * returns LMOSEM_ESTATE; lmosem_destroy still frees it).  Nothing runs on
+ * the device for the failing launch. */
+lmosem_status lmosem_inject_failure(lmosem_ctx *ctx);
 
 /* Replay each global iteration of lmosem_iterate / lmosem_reconstruct as one
  * captured HIP graph (1, the default) or launch kernel by kernel (0); an

@@ -44,6 +44,11 @@ struct lmosem_ctx {
     int64_t launches[4] = {0, 0, 0, 0};
     double ms[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t net_pairs = 0;     // pairs of the timed network launches
+    // device memory: the cap (0 = none) on what the context holds, and the
+    // bytes held by its live event sets
+    int64_t mem_cap = 0;
+    int64_t set_bytes = 0;
+    bool inject_failure = false;   // the next launch reports a HIP failure (testing hook)
 };
 
 // Workspace of one prepared event set.
@@ -66,6 +71,7 @@ struct lmosem_evset {
     uint8_t *near = nullptr;  // surrogate: near-field flag per pair [pair_cap]
     float *y = nullptr;       // surrogate: network outputs [pair_cap]
     size_t pb_chunks = 0;     // chunk rows allocated in pb
+    int64_t bytes = 0;        // device bytes held by the set (counted in its context's set_bytes)
 };
 
 namespace {
@@ -154,12 +160,30 @@ void drop_graphs(lmosem_evset *s) {
 
 void free_set(lmosem_evset *s) {
     if (!s) return;
+    if (s->s.ctx) s->s.ctx->set_bytes -= s->bytes;
     drop_graphs(s);
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->Hc); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
     hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->near); hipFree(s->y); hipFree(s->s.ang);
     delete s;
+}
+
+// Device bytes a set holds with its current plan and workspace.
+int64_t set_device_bytes(const lmosem_ctx *c, const lmosem_evset *s) {
+    const Geo &g = c->g;
+    const EvSet &v = s->s;
+    const int64_t n = std::max<int64_t>(v.n, 1), rows = std::max(v.max_rows, 1);
+    const int64_t chunks = std::max<int64_t>((int64_t)s->pb_chunks, 1);
+    const int64_t n_tiles = std::max<int64_t>(v.tile_off.empty() ? 1 : v.tile_off.back(), 1);
+    const int64_t n_chunks = std::max<int64_t>(v.chunk_off.empty() ? 1 : v.chunk_off.back(), 1);
+    int64_t b = 20 * n + (int64_t)sizeof(Tile) * n_tiles + (int64_t)sizeof(Chunk) * n_chunks +
+                8 * (int64_t)g.n_subsets * (v.n_real + 1);
+    b += 4 * rows * g.n_qpad + 4 * rows * forward_groups(g) + 8 * rows + 4 * chunks * g.n_qpad +
+         4 * (int64_t)v.n_real * g.n_qpad + 8 * (int64_t)v.n_real;
+    if (c->surrogate) b += 24 * rows + (8 * 4 + 4 + 1) * kPairCap;
+    if (s->Hc) b += 4 * n * g.n_qpad;
+    return b;
 }
 
 // (Re)allocate the per-set workspace for the current tile plan.
@@ -185,7 +209,19 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
         AL(s->near, (size_t)kPairCap);
     }
 #undef AL
+    c->set_bytes -= s->bytes;
+    s->bytes = set_device_bytes(c, s);
+    c->set_bytes += s->bytes;
     return LMOSEM_OK;
+}
+
+bool over_cap(const lmosem_ctx *c, int64_t more) {
+    return c->mem_cap > 0 && c->table_bytes + c->set_bytes + more > c->mem_cap;
+}
+
+std::string cap_msg(const lmosem_ctx *c, const char *what, int64_t more) {
+    return std::string(what) + " would take the context to " + std::to_string(c->table_bytes + c->set_bytes + more) +
+           " device bytes, above its cap of " + std::to_string(c->mem_cap) + " (lmosem_set_memory_cap)";
 }
 
 lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batch *batch, int force_subset,
@@ -214,6 +250,11 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
     }
     lmosem_status ws = alloc_workspace(c, s);
     if (ws != LMOSEM_OK) { free_set(s); return ws; }
+    if (over_cap(c, 0)) {
+        const std::string msg = cap_msg(c, "the event set", 0);
+        free_set(s);
+        return set_err(c, LMOSEM_ENOMEM, msg);
+    }
     *out = s;
     return LMOSEM_OK;
 }
@@ -223,6 +264,7 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
 // of the learned-scatter rows).
 template <class F>
 hipError_t timed(lmosem_ctx *c, int kind, F &&launch, hipStream_t st) {
+    if (c->inject_failure) { c->inject_failure = false; return hipErrorLaunchFailure; }
     if (!c->timing) return launch();
     lmosem_ctx::Pending p{nullptr, nullptr, kind};
     hipError_t e;
@@ -240,6 +282,7 @@ hipError_t timed(lmosem_ctx *c, int kind, F &&launch, hipStream_t st) {
 // covers the kernel alone, as a profiler's kernel trace does.
 template <class F>
 hipError_t timed_kernel(lmosem_ctx *c, int kind, F &&launch) {
+    if (c->inject_failure) { c->inject_failure = false; return hipErrorLaunchFailure; }
     if (!c->timing) return launch(nullptr);
     lmosem_ctx::Pending p{nullptr, nullptr, kind};
     hipError_t e;
@@ -432,6 +475,11 @@ lmosem_status iterate_set(lmosem_ctx *c, lmosem_evset *s, int n_iters, double *l
 // allocated and leaves the context usable (ENOMEM for a table too large)
 lmosem_status ensure_paths(lmosem_ctx *c) {
     if (c->paths_ready) return LMOSEM_OK;
+    const Geo &g = c->g;
+    // the exact path's tables have a known size: refused before any allocation
+    const int64_t predicted = (c->surrogate ? 0 : (int64_t)sizeof(float2) * g.n_angles * g.n_rpad * g.n_qpad) +
+                              4 * (int64_t)g.n_angles * g.n_p + 4 * (int64_t)(g.n_subsets + 1) * g.n_qpad;
+    if (over_cap(c, predicted)) return set_err(c, LMOSEM_ENOMEM, cap_msg(c, "the path tables", predicted));
     const auto t0 = std::chrono::steady_clock::now();
     std::string err;
     int64_t bytes = 0;
@@ -443,6 +491,15 @@ lmosem_status ensure_paths(lmosem_ctx *c) {
         c->t.T = nullptr; c->t.prim = nullptr; c->t.sens = nullptr; c->t.sens_all = nullptr;
         c->t.band = nullptr; c->t.band_lo = nullptr;
         return alloc_err(c, ("path tables: " + err).c_str(), e);
+    }
+    if (over_cap(c, bytes)) {   // the near-field band's width is known only once built
+        const std::string msg = cap_msg(c, "the path tables", bytes);
+        hipStreamSynchronize(c->st);
+        hipFree(c->t.T); hipFree(c->t.prim); hipFree(c->t.sens); hipFree(c->t.sens_all);
+        hipFree(c->t.band); hipFree(c->t.band_lo);
+        c->t.T = nullptr; c->t.prim = nullptr; c->t.sens = nullptr; c->t.sens_all = nullptr;
+        c->t.band = nullptr; c->t.band_lo = nullptr;
+        return set_err(c, LMOSEM_ENOMEM, msg);
     }
     c->table_bytes += bytes;
     c->table_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -835,6 +892,25 @@ lmosem_status lmosem_set_surrogate(lmosem_ctx *c, lmosem_net *net) {
     return LMOSEM_OK;
 }
 
+lmosem_status lmosem_set_memory_cap(lmosem_ctx *c, int64_t bytes) {
+    GUARD(c);
+    if (bytes < 0) return set_err(c, LMOSEM_EINVAL, "the memory cap must be >= 0");
+    c->mem_cap = bytes;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_memory_held(const lmosem_ctx *c, int64_t *bytes) {
+    if (!c || !bytes) return LMOSEM_EINVAL;
+    *bytes = c->table_bytes + c->set_bytes;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_inject_failure(lmosem_ctx *c) {
+    GUARD(c);
+    c->inject_failure = true;
+    return LMOSEM_OK;
+}
+
 lmosem_status lmosem_set_graphs(lmosem_ctx *c, int32_t enable) {
     GUARD(c);
     c->graphs = enable != 0;
@@ -1030,16 +1106,24 @@ lmosem_status lmosem_cache_rows(lmosem_ctx *c, lmosem_evset *s, int32_t enable) 
     if (!enable) {
         hipFree(s->Hc);
         s->Hc = nullptr;
+        c->set_bytes -= s->bytes;
+        s->bytes = set_device_bytes(c, s);
+        c->set_bytes += s->bytes;
         return LMOSEM_OK;
     }
     if (s->Hc) return LMOSEM_OK;
     const size_t n = (size_t)std::max<int64_t>(s->s.n, 1) * c->g.n_qpad;
+    if (over_cap(c, (int64_t)(sizeof(float) * n)))
+        return set_err(c, LMOSEM_ENOMEM, cap_msg(c, "the row cache", (int64_t)(sizeof(float) * n)));
     hipError_t e = hipMalloc(&s->Hc, sizeof(float) * n);
     if (e != hipSuccess) {
         s->Hc = nullptr;
         (void)hipGetLastError();
         return set_err(c, LMOSEM_ENOMEM, "row cache: " + std::to_string(sizeof(float) * n) + " bytes not available");
     }
+    c->set_bytes -= s->bytes;
+    s->bytes = set_device_bytes(c, s);
+    c->set_bytes += s->bytes;
     // zero padding columns (the learned-scatter rows never write them)
     e = launch_fill(s->Hc, n, 0.0f, c->st);
     return e == hipSuccess ? LMOSEM_OK : dev_err(c, "row cache", e);

@@ -90,6 +90,9 @@ _sigs = {
     "lmosem_autotune": (_S, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
+    "lmosem_set_memory_cap": (_S, [_P, ctypes.c_int64]),
+    "lmosem_memory_held": (_S, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lmosem_inject_failure": (_S, [_P]),
     "lmosem_cache_rows": (_S, [_P, _P, ctypes.c_int32]),
     "lmosem_bin_events": (_S, [_P, ctypes.POINTER(lmosem_events), ctypes.c_int32, _P, ctypes.c_int32, _P]),
     "lmosem_emission_mask": (_S, [_P, _P, ctypes.c_double, ctypes.c_int32, _P]),
@@ -288,6 +291,20 @@ def lmosem_autotune(ctx, evset) -> tuple:
 
 def lmosem_set_graphs(ctx, enable: bool):
     _check(ctx, _lib.lmosem_set_graphs(ctx, 1 if enable else 0))
+
+
+def lmosem_set_memory_cap(ctx, nbytes: int):
+    _check(ctx, _lib.lmosem_set_memory_cap(ctx, int(nbytes)))
+
+
+def lmosem_memory_held(ctx) -> int:
+    out = ctypes.c_int64()
+    _check(ctx, _lib.lmosem_memory_held(ctx, ctypes.byref(out)))
+    return out.value
+
+
+def lmosem_inject_failure(ctx):
+    _check(ctx, _lib.lmosem_inject_failure(ctx))
 
 
 def lmosem_cache_rows(ctx, evset, enable: bool):
