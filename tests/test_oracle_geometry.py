@@ -190,3 +190,39 @@ def test_line_extent_oblique_matches_dense_sampling():
             continue
         assert ext[0] == pytest.approx(t[hit][0], abs=2 * step)
         assert ext[1] == pytest.approx(t[hit][-1], abs=2 * step)
+
+
+@pytest.mark.parametrize("a", [0, 4])
+def test_column_attenuation_feature_is_response_weighted_row_integrals(a):
+    """The surrogate's response-weighted attenuation input (feature 4, ck / 2)
+    at an axis-aligned angle: summing mu dx k(u - u_s) pixel by pixel is the
+    same as summing, over the grid rows (or columns) that face the detector,
+    the line integral of mu along that row's centre line times the row's
+    position response k(u - u_row).  The line integrals come from the oracle's
+    Siddon routine, pinned above; the equality fails for a wrong pixel
+    weight, a wrong detector axis or response."""
+    n, dx = 16, 0.8
+    idx = (np.arange(n) - (n - 1) / 2) * dx
+    X, Y = np.meshgrid(idx, idx)
+    inside = X ** 2 + Y ** 2 <= (7 * dx) ** 2
+    mu = np.where(inside, 0.15 + np.where(X > 2.0, 0.1, 0.0), 0.0)   # a disk, denser on one side
+    g = _geom(n, dx, n_angles=16)
+    m = O.OracleModel(g, mu)
+    sig = dx / (2 * math.sqrt(2 * math.log(2)))
+
+    def k(x):
+        return max(math.exp(-x * x / (2 * sig * sig)) - math.exp(-4.5), 0.0)
+
+    th = 2 * math.pi * a / 16
+    nvec = np.array([math.cos(th), math.sin(th)])
+    tvec = np.array([-math.sin(th), math.cos(th)])
+    far = 4 * n * dx
+    for u in (-3.31, -0.4, 0.05, 1.77, 4.9):
+        ref = 0.0
+        for r in idx:   # the row (a = 0) or column (a = 4) centre lines facing the detector
+            foot = r * tvec
+            ref += O.line_integral(mu, dx, foot - far * nvec, foot + far * nvec) * k(u - r)
+        pix = int(m.support[0])
+        got = 2.0 * O.surrogate_features(m, pix, a, u, 140.0)[4]
+        assert got == pytest.approx(ref, rel=1e-12, abs=1e-15)
+    assert inside.sum() == len(m.support)
