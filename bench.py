@@ -134,12 +134,13 @@ def cpu_baseline(w, act, mu, ev, n_sample=2048, seed=11):
 
 
 # The fused network per (event, pixel) pair: 384 GELUs of five full-rate
-# operations and two transcendentals (exp2, rcp), 192 packed bf16
-# conversions and the output row (128 bf16 widenings + 128 FMAs): 2,368
-# full-rate lane-ops at FMA_LANES and 768 transcendental lane-ops at
-# TRANS_LANES per CU and clock, 42.5 CU-clocks per pair.  The MFMA work
-# (67,840 flops per pair at 2.5 PFLOP/s, 16.7 CU-clocks) runs beside it.
-MLP_FULL_OPS, MLP_TRANS_OPS = 384 * 5 + 192 + 256, 384 * 2
+# operations and two transcendentals (exp2, rcp) and 192 packed bf16
+# conversions: 2,112 full-rate lane-ops at FMA_LANES and 768 transcendental
+# lane-ops at TRANS_LANES per CU and clock, 40.5 CU-clocks per pair.  The
+# MFMA work (67,840 useful flops per pair, the output row included; 77,824
+# as issued, with layer 1's inputs padded to 32 and the output row's fifteen
+# zero rows) runs beside it at 2.5 PFLOP/s in 19.1 CU-clocks.
+MLP_FULL_OPS, MLP_TRANS_OPS = 384 * 5 + 192, 384 * 2
 MLP_PEAK_PAIRS = N_CU * CLK / (MLP_FULL_OPS / FMA_LANES + MLP_TRANS_OPS / TRANS_LANES)
 MLP_FLOPS_PER_PAIR = 2 * (8 * 128 + 2 * 128 * 128 + 128)
 BF16_PEAK_FLOPS = 2.5e15   # MI355X dense bf16 MFMA

@@ -16,11 +16,11 @@
 #include <vector>
 
 #include "lmosem_int.h"
+#include "mlp_infer.h"
 
 namespace lmo {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __host__ inline uint16_t f2bf(float f) {
     uint32_t u;
@@ -132,7 +132,6 @@ hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, floa
 // ---------------------------------------------------------------- network state
 // Parameter order (flat FP32 master copy): W1[8][128] b1[128] W2[128][128] b2
 // W3[128][128] b3 W4[128][1] b4[1]; W[in][out].
-constexpr int kIn = 8, kInPad = 16, kHid = 128;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kIn * kHid, kOffW2 = kOffB1 + kHid, kOffB2 = kOffW2 + kHid * kHid,
               kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kHid * kHid, kOffW4 = kOffB3 + kHid,
               kOffB4 = kOffW4 + kHid, kNParams = kOffB4 + 1;
@@ -311,34 +310,8 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // ---------------------------------------------------------------- fused inference
-// One kernel for the whole network.  The hidden units are the MFMA rows and
-// the samples the columns (Z^T[out][b] = sum_in W^T[out][in] H^T[in][b]), with
-// v_mfma_f32_16x16x32_bf16: a 16-row output block comes back with row
-// 4 (l/16) + v in register v of lane l (sample l % 16).  A 32-wide k-block over
-// inputs h0..h0+31 is permuted so that lane group g = l/16 holds inputs
-// {h0 + 4g .. +3} and {h0 + 16 + 4g .. +3} (the same permutation in the A and B
-// operands leaves the product unchanged): exactly the rows lane l holds of the
-// previous layer's output blocks 2 kb and 2 kb + 1, so activations stay in
-// registers from layer to layer.  The weights, pre-permuted into A-operand
-// lane order, the biases and the output row sit in LDS (75.8 KB), shared by
-// the twelve waves of one workgroup per CU; each wave takes 32 samples per
-// step (148 VGPRs, so three waves per SIMD).
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
-constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
-constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
-constexpr int kFB = 4 * kHid + 1;                // b1 b2 b3, w4 (bf16 values), b4
-constexpr int kFusedNB = 2;                      // 16-sample column blocks per wave
-constexpr int kFusedWaves = 12;                  // one workgroup per CU: 3 waves per SIMD share one LDS copy
-constexpr int kFusedThreads = 64 * kFusedWaves;
-constexpr int kFusedTile = kFusedWaves * 16 * kFusedNB;   // samples per workgroup step
-// gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
-// rewritten with one exp2 and one reciprocal
-constexpr float kGeluK0 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;
-constexpr float kGeluK1 = kGeluK0 * 0.044715f;
-
-__device__ __host__ inline int perm_k(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
-
+// (the kernel: mlp_infer.h) packed weights: A operands in lane order, biases
+// and the output row
 __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__ fw, float *__restrict__ fb) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < kFW1) {
@@ -363,119 +336,13 @@ __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__
     }
 }
 
-__device__ inline float gelu_fast(float z) {
-    const float t = z * fmaf(kGeluK1, z * z, kGeluK0);
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-t));
-}
-
-// bias-initialised accumulators of output block ob for this lane's rows
-__device__ inline f32x4 bias4(const float *b, int ob, int g) {
-    return *reinterpret_cast<const f32x4 *>(b + 16 * ob + 4 * g);
-}
-
-// one 128 -> 128 layer with GELU, activations in and out as B operands
-__device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
-                                    bf16x8 (&act)[4][kFusedNB]) {
-    bf16x8 nxt[4][kFusedNB];
-#pragma unroll
-    for (int ob = 0; ob < 8; ++ob) {
-        f32x4 acc[kFusedNB];
-        const f32x4 bv = bias4(b, ob, g);
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = bv;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const bf16x8 a = w[(ob * 4 + kb) * 64 + lane];
-#pragma unroll
-            for (int nb = 0; nb < kFusedNB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], acc[nb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[nb][v]);
-    }
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
-}
-
-__global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__restrict__ fw, const float *__restrict__ fb,
-                                                 const float *__restrict__ X, int64_t n, float *__restrict__ y) {
-    __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
-    __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(fw);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_w);
-        for (int i = threadIdx.x; i < kFWTotal / 8; i += kFusedThreads) dst[i] = src[i];
-        for (int i = threadIdx.x; i < kFB; i += kFusedThreads) s_b[i] = fb[i];
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane >> 4, r = lane & 15;
-    const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
-    const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
-    const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
-    const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        // keep the weight reads inside the loop (hoisting them would need
-        // 288 registers)
-        __asm__ volatile("" ::: "memory");
-        const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
-        // layer 1: the inputs as B operands (lane groups 0 and 1 hold
-        // features 0..3 and 4..7; every other slot is zero)
-        bf16x8 act[4][kFusedNB];
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) {
-            const int64_t p = base + 16 * nb + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (g < 2 && p < n) v = *reinterpret_cast<const float4 *>(X + p * kIn + 4 * g);
-            const bf16x8 xin = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
-                                (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-            act[0][nb] = xin;
-        }
-        {
-            bf16x8 nxt[4][kFusedNB];
-#pragma unroll
-            for (int ob = 0; ob < 8; ++ob) {
-                const bf16x8 a = w1[ob * 64 + lane];
-                const f32x4 bv = bias4(s_b, ob, g);
-#pragma unroll
-                for (int nb = 0; nb < kFusedNB; ++nb) {
-                    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[0][nb], bv, 0, 0, 0);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[v]);
-                }
-            }
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-                for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
-        }
-        hidden_layer(w2, s_b + kHid, lane, g, act);
-        hidden_layer(w3, s_b + 2 * kHid, lane, g, act);
-        // output row: this lane's 32 hidden units, then the sum over the 4 lane groups
-        float part[kFusedNB];
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) part[nb] = 0.0f;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float w4 = s_b[3 * kHid + 32 * kb + perm_k(g, i)];
-#pragma unroll
-                for (int nb = 0; nb < kFusedNB; ++nb) part[nb] = fmaf(w4, (float)act[kb][nb][i], part[nb]);
-            }
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) {
-            part[nb] += __shfl_xor(part[nb], 16, 64);
-            part[nb] += __shfl_xor(part[nb], 32, 64);
-            const int64_t p = base + 16 * nb + r;
-            if (g == 0 && p < n) y[p] = part[nb] + s_b[4 * kHid];
-        }
-    }
-}
+// samples from an array X[n][8], outputs to y[n]
+struct XSource {
+    const float *X;
+    float *y;
+    __device__ float4 inputs(int64_t p, int g) const { return *reinterpret_cast<const float4 *>(X + p * kIn + 4 * g); }
+    __device__ void output(int64_t p, float v) const { y[p] = v; }
+};
 
 // per-epoch loss: fixed-order sum of the minibatch's partial sums
 __global__ void k_loss_add(const double *__restrict__ parts, int nparts, double *__restrict__ loss) {
@@ -626,7 +493,8 @@ hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStrea
     if (count <= 0) return hipSuccess;
     const int64_t tiles = (count + kFusedTile - 1) / kFusedTile;
     const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256);   // one workgroup per CU
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(kFusedThreads), 0, st, n->fw, n->fb, X, count, y);
+    hipLaunchKernelGGL(k_mlp_infer<XSource>, dim3(grid), dim3(kFusedThreads), 0, st, n->fw, n->fb,
+                       XSource{X, y}, count);
     return hipGetLastError();
 }
 

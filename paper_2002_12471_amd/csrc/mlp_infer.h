@@ -1,0 +1,173 @@
+// The fused inference kernel of the scatter-surrogate network (8 -> 128 ->
+// 128 -> 128 -> 1, GELU in its tanh form, bf16 MFMA with FP32 accumulation),
+// as a template over where its inputs come from and where its outputs go:
+// a sample array (lmosem_net_forward) or the (event, pixel) pairs of a
+// learned-scatter sub-iteration, whose inputs are formed in the kernel.
+//
+// Src provides  __device__ float4 inputs(int64_t p, int g) const : inputs
+// 4g .. 4g+3 of sample p (g = 0, 1), and  __device__ void output(int64_t p,
+// float y) const : the network's output for sample p.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lmo {
+
+constexpr int kIn = 8, kInPad = 16, kHid = 128;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One kernel for the whole network.  The hidden units are the MFMA rows and
+// the samples the columns (Z^T[out][b] = sum_in W^T[out][in] H^T[in][b]), with
+// v_mfma_f32_16x16x32_bf16: a 16-row output block comes back with row
+// 4 (l/16) + v in register v of lane l (sample l % 16).  A 32-wide k-block over
+// inputs h0..h0+31 is permuted so that lane group g = l/16 holds inputs
+// {h0 + 4g .. +3} and {h0 + 16 + 4g .. +3} (the same permutation in the A and B
+// operands leaves the product unchanged): exactly the rows lane l holds of the
+// previous layer's output blocks 2 kb and 2 kb + 1, so activations stay in
+// registers from layer to layer.  The output row is one more MFMA product
+// whose A operand has W4 in its first row and zeros elsewhere (wasted matrix
+// rows are cheaper than 128 widenings and FMAs per sample on the vector ALU,
+// which bounds the kernel).  The weights, pre-permuted into A-operand lane
+// order, the biases and the output row sit in LDS (80 KB), shared by the
+// sixteen waves of one workgroup per CU; each wave takes 32 samples per step
+// (123 VGPRs, four waves per SIMD).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
+constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
+constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
+constexpr int kFB = 4 * kHid + 1;                // b1 b2 b3, w4 (bf16 values), b4
+constexpr int kFusedNB = 2;                      // 16-sample column blocks per wave
+constexpr int kFusedWaves = 16;                  // one workgroup per CU: 4 waves per SIMD share one LDS copy
+constexpr int kFusedThreads = 64 * kFusedWaves;
+constexpr int kFusedTile = kFusedWaves * 16 * kFusedNB;   // samples per workgroup step
+// gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
+// rewritten with one exp2 and one reciprocal
+constexpr float kGeluK0 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kGeluK1 = kGeluK0 * 0.044715f;
+
+__device__ __host__ inline int perm_k(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
+
+__device__ inline float gelu_fast(float z) {
+    const float t = z * fmaf(kGeluK1, z * z, kGeluK0);
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-t));
+}
+
+// bias-initialised accumulators of output block ob for this lane's rows
+__device__ inline f32x4 bias4(const float *b, int ob, int g) {
+    return *reinterpret_cast<const f32x4 *>(b + 16 * ob + 4 * g);
+}
+
+// one 128 -> 128 layer with GELU, activations in and out as B operands
+__device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
+                                    bf16x8 (&act)[4][kFusedNB]) {
+    bf16x8 nxt[4][kFusedNB];
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) {
+        f32x4 acc[kFusedNB];
+        const f32x4 bv = bias4(b, ob, g);
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = bv;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = w[(ob * 4 + kb) * 64 + lane];
+#pragma unroll
+            for (int nb = 0; nb < kFusedNB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], acc[nb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[nb][v]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
+}
+
+template <class Src>
+__global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__restrict__ fw,
+                                                             const float *__restrict__ fb, Src src, int64_t n) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
+    __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w4[4 * 64 * 8];
+    {
+        const uint4 *w_src = reinterpret_cast<const uint4 *>(fw);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_w);
+        for (int i = threadIdx.x; i < kFWTotal / 8; i += kFusedThreads) dst[i] = w_src[i];
+        for (int i = threadIdx.x; i < kFB; i += kFusedThreads) s_b[i] = fb[i];
+        // the output row as the A operand of an MFMA whose first row is W4
+        // (every other row zero), k-blocks permuted as the hidden layers' are;
+        // the stored W4 values are bf16 already
+        for (int i = threadIdx.x; i < 4 * 64 * 8; i += kFusedThreads) {
+            const int kb = i >> 9, l = (i >> 3) & 63, e = i & 7;
+            s_w4[i] = (l & 15) == 0 ? (__bf16)fb[3 * kHid + 32 * kb + perm_k(l >> 4, e)] : (__bf16)0.0f;
+        }
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
+    const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
+    const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
+    const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // keep the weight reads inside the loop (hoisting them would need
+        // 288 registers)
+        __asm__ volatile("" ::: "memory");
+        const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
+        // layer 1: the inputs as B operands (lane groups 0 and 1 hold
+        // features 0..3 and 4..7; every other slot is zero)
+        bf16x8 act[4][kFusedNB];
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) {
+            const int64_t p = base + 16 * nb + r;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (g < 2 && p < n) v = src.inputs(p, g);
+            const bf16x8 xin = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
+                                (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+            act[0][nb] = xin;
+        }
+        {
+            bf16x8 nxt[4][kFusedNB];
+#pragma unroll
+            for (int ob = 0; ob < 8; ++ob) {
+                const bf16x8 a = w1[ob * 64 + lane];
+                const f32x4 bv = bias4(s_b, ob, g);
+#pragma unroll
+                for (int nb = 0; nb < kFusedNB; ++nb) {
+                    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[0][nb], bv, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[v]);
+                }
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
+        }
+        hidden_layer(w2, s_b + kHid, lane, g, act);
+        hidden_layer(w3, s_b + 2 * kHid, lane, g, act);
+        // output row on the MFMA: row 0 of the product holds y, in register 0
+        // of lanes 0-15 (sample r of each 16-sample block)
+        const bf16x8 *w4 = reinterpret_cast<const bf16x8 *>(s_w4);
+        f32x4 o[kFusedNB];
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = w4[kb * 64 + lane];
+#pragma unroll
+            for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], o[nb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) {
+            const int64_t p = base + 16 * nb + r;
+            if (g == 0 && p < n) src.output(p, o[nb][0] + s_b[4 * kHid]);
+        }
+    }
+}
+
+
+}  // namespace lmo
