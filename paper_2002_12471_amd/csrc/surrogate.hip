@@ -218,18 +218,24 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_an
 
 // Inference, step 2: the near field, exact.  The emission pixels within the
 // event's own position response (|u - u_q| < 3 sig_u) are exactly the
-// emission pixels among the path ends the event reaches (its rank range), so
-// one block per event row walks that range: each group of 16 lanes takes one
-// such pixel q, its lanes share the scatter terms of the ends the event
-// reaches (all inside q's band, stored contiguously per q, so the group's
-// loads are contiguous), and the group's first lane adds the primary term,
-// writes H and flags the pair as near.
+// emission pixels among the path ends it reaches (its rank range), so one
+// block per event row walks that range: the event's position response at
+// every reached path end is staged in LDS first (one exp and an FP64 offset
+// per path end instead of per term), then each group of 16 lanes takes one
+// such pixel q, its lanes share the scatter terms of the reached ends (all
+// inside q's band, stored contiguously per q, so the group's loads are
+// contiguous), and the group's first lane adds the primary term, writes H
+// and flags the pair as near.  Ranges longer than the staging buffer fall
+// back to evaluating the response per term.
+constexpr int kNearStage = 2048;
+
 __global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const float2 *__restrict__ band, int band_w,
                                                    const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
                                                    const float *__restrict__ su, const float *__restrict__ se,
                                                    const float *__restrict__ efac, const int2 *__restrict__ rr,
                                                    int row_base, int j0, int rows, float *__restrict__ H,
                                                    uint8_t *__restrict__ near) {
+    __shared__ float Kr[kNearStage];
     const int lr = blockIdx.x;   // row within the batch
     if (lr >= rows) return;
     const int jr = j0 + lr, j = row_base + jr;
@@ -240,6 +246,10 @@ __global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const f
     const double *us = st.us_sorted + (size_t)a * g.n_p;
     const int *ss = st.s_sorted + (size_t)a * g.n_p;
     const float inv2s2 = (float)(1.0 / (2.0 * g.sig_u * g.sig_u));
+    const bool staged = r.y - r.x <= kNearStage;
+    if (staged)
+        for (int i = threadIdx.x; i < r.y - r.x; i += blockDim.x) Kr[i] = k_resp_f((float)(u - us[r.x + i]), inv2s2);
+    __syncthreads();
     const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
     // every group runs the same number of passes, so the 16-lane sums below
     // always see all of their lanes
@@ -251,17 +261,27 @@ __global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const f
             const int lo = band_lo[(size_t)a * g.n_p + q];
             const float2 *bq = band + ((size_t)a * g.n_qpad + q) * band_w;
             const int b0 = max(r.x - lo, 0), b1 = min(r.y - lo, band_w);
-            for (int b = b0 + l; b < b1; b += 16) {
-                const float2 ab = bq[b];
-                h = fmaf(k_resp_f((float)(u - us[lo + b]), inv2s2), __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)), h);
+            if (staged) {
+                const float *kq = Kr + (lo - r.x);
+#pragma unroll 4
+                for (int b = b0 + l; b < b1; b += 16) {
+                    const float2 ab = bq[b];
+                    h = fmaf(kq[b], __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)), h);
+                }
+            } else {
+                for (int b = b0 + l; b < b1; b += 16) {
+                    const float2 ab = bq[b];
+                    h = fmaf(k_resp_f((float)(u - us[lo + b]), inv2s2), __builtin_amdgcn_exp2f(fmaf(ab.y, et, ab.x)),
+                             h);
+                }
             }
         }
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) h += __shfl_xor(h, off, 64);
         if (l == 0 && q < g.n_q) {
             const float beta0 = (float)(2.0 * g.c2 * (g.e0 - g.e_c));
-            h += k_resp_f((float)(u - us[rank]), inv2s2) *
-                 __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
+            const float kp = staged ? Kr[rank - r.x] : k_resp_f((float)(u - us[rank]), inv2s2);
+            h += kp * __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
             H[(size_t)jr * g.n_qpad + q] = h * efac[j];
             near[(size_t)lr * g.n_q + q] = 1;
         }
