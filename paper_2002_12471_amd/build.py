@@ -21,7 +21,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include")]
 # per-source extras: the network kernels keep MFMA accumulators in ordinary
 # VGPRs (no copies out of the accumulation registers before each activation)
-EXTRA = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "surrogate.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

@@ -67,16 +67,14 @@ struct lmosem_evset {
     bool rows_valid = false;  // Hc holds every row
     int use_graph = -1;       // autotuned choice (1 replay graphs, 0 launch directly), -1 = context setting
     float *col = nullptr;     // surrogate: per-sub-iteration event column features [max_rows][4] + ranks [max_rows][2]
-    float *X = nullptr;       // surrogate: network inputs [pair_cap][8]
-    uint8_t *near = nullptr;  // surrogate: near-field flag per pair [pair_cap]
-    float *y = nullptr;       // surrogate: network outputs [pair_cap]
+    uint16_t *X = nullptr;    // surrogate: network inputs [pair_cap][8], bf16
     size_t pb_chunks = 0;     // chunk rows allocated in pb
     int64_t bytes = 0;        // device bytes held by the set (counted in its context's set_bytes)
 };
 
 namespace {
 
-constexpr int64_t kPairCap = 1 << 22;   // (event, pixel) pairs per surrogate network batch (148 MB of inputs)
+constexpr int64_t kPairCap = 1 << 22;   // (event, pixel) pairs per surrogate network batch (64 MB of inputs)
 
 lmosem_status set_err(lmosem_ctx *c, lmosem_status s, const std::string &msg) {
     if (c) {
@@ -165,7 +163,7 @@ void free_set(lmosem_evset *s) {
     hipFree(s->s.u); hipFree(s->s.e); hipFree(s->s.efac); hipFree(s->s.orig); hipFree(s->s.tiles); hipFree(s->s.chunks);
     hipFree(s->s.crange); hipFree(s->s.rrange);
     hipFree(s->H); hipFree(s->Hc); hipFree(s->pmean); hipFree(s->mean); hipFree(s->inv); hipFree(s->pb); hipFree(s->f);
-    hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->near); hipFree(s->y); hipFree(s->s.ang);
+    hipFree(s->ll); hipFree(s->col); hipFree(s->X); hipFree(s->s.ang);
     delete s;
 }
 
@@ -181,7 +179,7 @@ int64_t set_device_bytes(const lmosem_ctx *c, const lmosem_evset *s) {
                 8 * (int64_t)g.n_subsets * (v.n_real + 1);
     b += 4 * rows * g.n_qpad + 4 * rows * forward_groups(g) + 8 * rows + 4 * chunks * g.n_qpad +
          4 * (int64_t)v.n_real * g.n_qpad + 8 * (int64_t)v.n_real;
-    if (c->surrogate) b += 24 * rows + (8 * 4 + 4 + 1) * kPairCap;
+    if (c->surrogate) b += 24 * rows + 8 * 2 * kPairCap;
     if (s->Hc) b += 4 * n * g.n_qpad;
     return b;
 }
@@ -204,9 +202,7 @@ lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
     AL(s->ll, sizeof(double) * s->s.n_real);
     if (c->surrogate) {
         AL(s->col, 6 * sizeof(float) * (size_t)std::max(s->s.max_rows, 1));
-        AL(s->X, sizeof(float) * 8 * (size_t)kPairCap);
-        AL(s->y, sizeof(float) * (size_t)kPairCap);
-        AL(s->near, (size_t)kPairCap);
+        AL(s->X, sizeof(uint16_t) * 8 * (size_t)kPairCap);
     }
 #undef AL
     c->set_bytes -= s->bytes;
@@ -326,7 +322,7 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStre
             return timed(c, 3, launch, st);
         };
         return surrogate_rows(g, c->t, c->net, v.ang, v.u, v.e, v.efac, s->f, v.rrange + (size_t)i * (v.n_real + 1),
-                              v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->near, s->X, s->y, kPairCap, st,
+                              v.n_real, v.row_off[i], rows, H, s->pmean, s->col, s->X, kPairCap, st,
                               c->timing ? &wrap : nullptr);
     }
     return timed_kernel(c, 0, [&](const KernelEvents *ke) {

@@ -193,6 +193,8 @@ void net_destroy(Net *n);
 hipStream_t net_stream(const Net *n);   // the stream the network was created on
 hipError_t net_get_params(Net *n, float *host);
 hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStream_t st);
+// the packed weights of the fused inference kernel (mlp_infer.h)
+void net_fused_weights(const Net *n, const uint16_t **fw, const float **fb);
 hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host);
 hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
                      float lr_decay, double *loss_host);
@@ -205,7 +207,7 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
 using LaunchWrap = std::function<hipError_t(const std::function<hipError_t()> &)>;
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X, float *y,
+                          int row_base, int rows, float *H, float *pmean, float *col, uint16_t *X,
                           int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net = nullptr);
 
 // ---- ALU rate probes (probe.hip) ----

@@ -489,6 +489,11 @@ static hipError_t backward_batch(Net &n, const float *dy, int nb) {
     return hipGetLastError();
 }
 
+void net_fused_weights(const Net *n, const uint16_t **fw, const float **fb) {
+    *fw = n->fw;
+    *fb = n->fb;
+}
+
 hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int64_t tiles = (count + kFusedTile - 1) / kFusedTile;

@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "lmosem_int.h"
+#include "mlp_infer.h"
 #include "paths.h"
 
 namespace lmo {
@@ -196,10 +197,11 @@ __global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_
 }
 
 // Inference, step 1: for rows [j0, j0 + rows) of the sub-iteration and every
-// emission pixel q, the network inputs; H and the near-field flag start at 0.
+// emission pixel q, the network inputs, rounded to bf16 here as the network
+// would round them (16 bytes per pair).
 __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
                              const float *__restrict__ se, const float4 *__restrict__ col, int row_base, int j0,
-                             int rows, float *__restrict__ H, uint8_t *__restrict__ near, float *__restrict__ X) {
+                             int rows, uint16_t *__restrict__ X) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch < 2^31
     if (k >= rows * g.n_q) return;
     const int jr = j0 + k / g.n_q, q = k % g.n_q;
@@ -207,16 +209,41 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_an
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
     const float et = se[j];   // E - e_c
-    H[(size_t)jr * g.n_qpad + q] = 0.0f;
-    near[k] = 0;
     float x[8];
     features(g, st, q, a, u, (double)et + g.e_c, col[j - row_base], x);
-    float4 *xo = reinterpret_cast<float4 *>(X + (size_t)k * 8);
-    xo[0] = make_float4(x[0], x[1], x[2], x[3]);
-    xo[1] = make_float4(x[4], x[5], x[6], x[7]);
+    uint4 packed;
+    uint32_t *w = reinterpret_cast<uint32_t *>(&packed);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * i]) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * i + 1]) << 16);
+    reinterpret_cast<uint4 *>(X)[k] = packed;
 }
 
-// Inference, step 2: the near field, exact.  The emission pixels within the
+// Inference, step 2: the network over the batch's pairs, reading the bf16
+// inputs and writing S0 max(e^y - 1e-4, 0) into H for every pair (step 3
+// then overwrites the near field's pairs with their exact values).
+struct PairSource {
+    const uint16_t *X;
+    float *H;
+    int j0, n_q, n_qpad;
+    float s0, inv_nq;   // inv_nq = 1 / n_q: pair -> (row, pixel) without an integer division
+    __device__ float4 inputs(int64_t p, int gi) const {
+        const uint2 v = *reinterpret_cast<const uint2 *>(X + p * 8 + 4 * gi);
+        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+    }
+    __device__ void output(int64_t p, float y) const {
+        const int k = (int)p;   // < 2^22 pairs per batch: exact in FP32, and the quotient is off by at most one
+        int lr = (int)((float)k * inv_nq);
+        lr += (lr + 1) * n_q <= k ? 1 : 0;
+        lr -= lr * n_q > k ? 1 : 0;
+        const int q = k - lr * n_q;
+        H[(size_t)(j0 + lr) * n_qpad + q] = s0 * fmaxf(__expf(y) - kTargetFloor, 0.0f);
+    }
+};
+
+// Inference, step 3: the near field, exact.  The emission pixels within the
 // event's own position response (|u - u_q| < 3 sig_u) are exactly the
 // emission pixels among the path ends it reaches (its rank range), so one
 // block per event row walks that range: the event's position response at
@@ -224,8 +251,8 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_an
 // per path end instead of per term), then each group of 16 lanes takes one
 // such pixel q, its lanes share the scatter terms of the reached ends (all
 // inside q's band, stored contiguously per q, so the group's loads are
-// contiguous), and the group's first lane adds the primary term, writes H
-// and flags the pair as near.  Ranges longer than the staging buffer fall
+// contiguous), and the group's first lane adds the primary term and writes
+// H over the network's value.  Ranges longer than the staging buffer fall
 // back to evaluating the response per term.
 constexpr int kNearStage = 2048;
 
@@ -233,8 +260,7 @@ __global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const f
                                                    const int *__restrict__ band_lo, const int *__restrict__ ev_angle,
                                                    const float *__restrict__ su, const float *__restrict__ se,
                                                    const float *__restrict__ efac, const int2 *__restrict__ rr,
-                                                   int row_base, int j0, int rows, float *__restrict__ H,
-                                                   uint8_t *__restrict__ near) {
+                                                   int row_base, int j0, int rows, float *__restrict__ H) {
     __shared__ float Kr[kNearStage];
     const int lr = blockIdx.x;   // row within the batch
     if (lr >= rows) return;
@@ -283,20 +309,8 @@ __global__ __launch_bounds__(256) void k_surr_near(Geo g, SurrTables st, const f
             const float kp = staged ? Kr[rank - r.x] : k_resp_f((float)(u - us[rank]), inv2s2);
             h += kp * __builtin_amdgcn_exp2f(fmaf(beta0, et, st.prim[(size_t)a * g.n_p + q]));
             H[(size_t)jr * g.n_qpad + q] = h * efac[j];
-            near[(size_t)lr * g.n_q + q] = 1;
         }
     }
-}
-
-// Inference, step 4 (after the network, step 3): add the network's scatter
-// estimate to the far-field pairs.
-__global__ void k_surr_add(Geo g, int j0, int rows, const uint8_t *__restrict__ near, const float *__restrict__ y,
-                           float *__restrict__ H) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= rows * g.n_q || near[k]) return;
-    const int jr = j0 + k / g.n_q, q = k % g.n_q;
-    const float s0 = (float)(1.0 / (g.dx * g.sig_e));
-    H[(size_t)jr * g.n_qpad + q] += s0 * fmaxf(__expf(y[k]) - kTargetFloor, 0.0f);
 }
 
 // partial means with one pixel group: pmean[j] = sum_q f[real(j)][q] H[j][q]
@@ -314,6 +328,18 @@ __global__ void k_row_mean(Geo g, const int *__restrict__ rrange, int n_real, in
     if (threadIdx.x == 0) pmean[j] = s;
 }
 
+// the fused network over a batch of pairs, one workgroup per CU as for
+// lmosem_net_forward
+static hipError_t launch_mlp_pairs(Net *net, const PairSource &src, int64_t pairs, hipStream_t st) {
+    const uint16_t *fw = nullptr;
+    const float *fb = nullptr;
+    net_fused_weights(net, &fw, &fb);
+    const int64_t tiles = (pairs + kFusedTile - 1) / kFusedTile;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256);
+    hipLaunchKernelGGL(k_mlp_infer<PairSource>, dim3(grid), dim3(kFusedThreads), 0, st, fw, fb, src, pairs);
+    return hipGetLastError();
+}
+
 hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel, const int32_t *angle,
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st) {
@@ -328,8 +354,8 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
 // H[j][q] = primary(q; A_j) + S_net(q; A_j), and the partial means (one group).
 hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev_angle, const float *su,
                           const float *se, const float *efac, const float *f, const int *rrange, int n_real,
-                          int row_base, int rows, float *H, float *pmean, float *col, uint8_t *near, float *X,
-                          float *y, int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net) {
+                          int row_base, int rows, float *H, float *pmean, float *col, uint16_t *X,
+                          int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net) {
     if (rows <= 0) return hipSuccess;
     SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     float4 *col4 = reinterpret_cast<float4 *>(col);
@@ -343,15 +369,13 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
         const int nr = std::min(rows_per, rows - j0);
         const int64_t pairs = (int64_t)nr * g.n_q;
         hipLaunchKernelGGL(k_surr_pairs, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, s, ev_angle, su,
-                           se, col4, row_base, j0, nr, H, near, X);
+                           se, col4, row_base, j0, nr, X);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_surr_near, dim3((unsigned)nr), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
-                           ev_angle, su, se, efac, rr, row_base, j0, nr, H, near);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        auto run_net = [&]() { return net_forward(net, X, pairs, y, st); };
+        const PairSource src{X, H, j0, g.n_q, g.n_qpad, (float)(1.0 / (g.dx * g.sig_e)), 1.0f / (float)g.n_q};
+        auto run_net = [&]() { return launch_mlp_pairs(net, src, pairs, st); };
         if ((e = wrap_net ? (*wrap_net)(run_net) : run_net()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_surr_add, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, g, j0, nr, near,
-                           y, H);
+        hipLaunchKernelGGL(k_surr_near, dim3((unsigned)nr), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
+                           ev_angle, su, se, efac, rr, row_base, j0, nr, H);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_row_mean, dim3(rows), dim3(64), 0, st, g, rrange, n_real, rows, H, f, pmean);
