@@ -1,6 +1,10 @@
 // Vector-ALU rate probes: how many FP32 FMAs, exp2s and forward-projection
 // terms (FMA, exp2, FMA) the GPU retires per second.  Each thread runs 16
 // independent dependency chains so that issue rate, not latency, bounds them.
+// The FMA probe keeps its operands in vector registers: an FMA that reads a
+// scalar register issues at 64 lanes per CU and clock, one on vector
+// registers alone at up to 128 (dual issue), which is what the published
+// FP32 rate counts.
 #include <hip/hip_runtime.h>
 
 #include "lmosem_int.h"
@@ -13,6 +17,7 @@ __global__ __launch_bounds__(256) void k_probe_fma(int iters, float m, float c, 
     float x[kChains];
 #pragma unroll
     for (int k = 0; k < kChains; ++k) x[k] = threadIdx.x * 1e-3f + k;
+    __asm__ volatile("" : "+v"(m), "+v"(c));   // the multiplier and addend in vector registers
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int k = 0; k < kChains; ++k) x[k] = fmaf(x[k], m, c);
