@@ -68,7 +68,7 @@ typedef enum {
                              memory cap (lmosem_set_memory_cap) */
     LMOSEM_EDEVICE = -4,  /* a HIP call failed; the context is poisoned */
     LMOSEM_ESTATE = -5,   /* context poisoned by an earlier device error */
-    LMOSEM_ENOTSUP = -6   /* valid but not supported by this build */
+    LMOSEM_ENOTSUP = -6   /* valid but not supported by this library */
 } lmosem_status;
 
 typedef struct lmosem_ctx lmosem_ctx;

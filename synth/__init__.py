@@ -55,7 +55,7 @@ def _load():
 
 
 def default_threads() -> int:
-    # the GPU machines give a process a share of 16 CPUs whatever os.cpu_count() says
+    # a process may be given a share of 16 CPUs whatever os.cpu_count() says
     return max(1, min(16, os.cpu_count() or 1))
 
 
