@@ -65,9 +65,9 @@ def mix_peak_terms_per_s():
     return N_CU * CLK / (2.0 / FMA_LANES + 1.0 / TRANS_LANES)
 
 
-def profiled_traffic(event_tile, workload, cached=False):
+def profiled_traffic(event_tile, pixel_tile, workload, cached=False):
     """HBM bytes per launch of the dominant kernel (the forward projection at
-    this event tile, or with cached rows the row-dot kernel) from the committed
+    this event and pixel tile, or with cached rows the row-dot kernel) from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
     changed since the counters were taken or the case was not profiled."""
     import hashlib
@@ -80,7 +80,8 @@ def profiled_traffic(event_tile, workload, cached=False):
                 k, v = line.split(":", 1)
                 fields[k.split(" (")[0].strip()] = v.strip()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        key = "traffic_bytes_per_launch_row_dot" if cached else f"traffic_bytes_per_launch_ev{event_tile}"
+        key = ("traffic_bytes_per_launch_row_dot" if cached
+               else f"traffic_bytes_per_launch_ev{event_tile}_px{pixel_tile}")
         if workload != "brain64" or fields.get("source_sha256") != sha or key not in fields:
             return None
         return float(fields[key])
@@ -551,6 +552,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--event-tile", type=int, default=0)
+    ap.add_argument("--pixel-tile", type=int, default=0,
+                    help="emission pixels per forward workgroup (64-256) with --event-tile; default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="brain64",
                     choices=["brain64", "tiny", "batch_tiny", "brain128", "surrogate", "surrogate128", "study"])
@@ -638,15 +641,18 @@ def main():
     torch.cuda.synchronize()
     t_create = time.time() - t0
     if args.event_tile:
-        ctx.set_tuning(args.event_tile)
+        ctx.set_tuning(args.event_tile, args.pixel_tile)
     t0 = time.time()
     evs = L.lmosem_events_load(ctx.handle, evd, offsets)
     torch.cuda.synchronize()
     t_load = time.time() - t0
     t0 = time.time()
-    tile, chunk, graphs = (L.lmosem_autotune(ctx.handle, evs) if not args.event_tile
-                           else (args.event_tile, 256, 1))
+    if not args.event_tile:
+        L.lmosem_autotune(ctx.handle, evs)
     t_tune = time.time() - t0
+    plan = L.lmosem_evset_plan(evs)
+    tile, chunk, graphs = plan["event_tile"], plan["chunk_rows"], plan["graphs"]
+    pixel_tile = 64 * plan["pixel_waves"]
     start = np.broadcast_to((mu > 0).astype(np.float32), (n_real,) + mu.shape).copy()
     img = torch.as_tensor(start if n_real > 1 else start[0], device=dev).contiguous()
     t_fill = None
@@ -711,7 +717,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": row_bytes / fwd_s / 1e9 / HBM_PEAK_GBS,
-            "traffic": None if emission is not None else profiled_traffic(tile, args.workload, cached=True),
+            "traffic": None if emission is not None else profiled_traffic(tile, pixel_tile, args.workload, cached=True),
             "per_unit": "4 bytes per (event, padded support pixel) of the sub-iteration's rows",
             "units_per_launch": row_bytes / 4,
             "avg_launch_ms": fwd_s * 1e3,
@@ -728,7 +734,7 @@ def main():
         "peak": peak_terms * FLOPS_PER_TERM / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved_terms / peak_terms,
-        "traffic": None if emission is not None else profiled_traffic(tile, args.workload),
+        "traffic": None if emission is not None else profiled_traffic(tile, pixel_tile, args.workload),
         "per_unit": "one inner term (event, emission pixel, path end with non-zero position "
                     "response) = 2 FMA + 1 exp2 = 5 flops; the kernel evaluates per-path weights "
                     "tabulated once per mu-map in FP64 (w G = 2^(alpha + beta (E - e_c)) times a per-event factor)",
@@ -759,7 +765,7 @@ def main():
                    "events": J, "realisations": n_real, "subsets": g["n_subsets"],
                    "support_pixels": int((mu > 0).sum()),
                    **({"emission_set": em_info} if emission is not None else {}),
-                   "event_tile": tile, "chunk_rows": chunk, "graphs": bool(graphs),
+                   "event_tile": tile, "pixel_tile": pixel_tile, "chunk_rows": chunk, "graphs": bool(graphs),
                    "path": "exact FP32" + (", system rows cached after the first iteration" if args.cache_rows
                                            else "")},
         "roofline": roof,

@@ -256,8 +256,17 @@ lmosem_status lmosem_iterate(lmosem_ctx *ctx, lmosem_evset *set, int32_t n_iters
  * creation; other values of it are ignored. */
 lmosem_status lmosem_set_tuning(lmosem_ctx *ctx, int32_t event_tile);
 
+/* Tuning: emission pixels per forward-projection workgroup (the pixel tile:
+ * 64, 128, 192 or 256, one wave of 64 threads per 64 pixels; 0 restores the
+ * default, the emission set's width up to 256) for event sets loaded
+ * afterwards; lmosem_autotune may replace it.  Results do not depend on it
+ * beyond FP32 summation order.  Errors: EINVAL. */
+lmosem_status lmosem_set_pixel_tile(lmosem_ctx *ctx, int32_t pixels);
+
 /* Autotuner: times the forward projection of the set's largest subset for
- * 8, 16 and 32 events per tile, the backprojection with the update that
+ * 8, 16 and 32 events per tile, each with pixel tiles of 64, 128 and 256
+ * emission pixels per workgroup (and the context's own, when the emission
+ * set is narrower), the backprojection with the update that
  * adds its chunk partials for 64-1024 rows per chunk (using the set's
  * scratch image), and one whole iteration launched kernel by kernel against one
  * replayed as a HIP graph (iterations estimated above 50 ms are replayed
@@ -288,6 +297,12 @@ lmosem_status lmosem_memory_held(const lmosem_ctx *ctx, int64_t *bytes);
  * returns LMOSEM_ESTATE; lmosem_destroy still frees it).  Nothing runs on
  * the device for the failing launch. */
 lmosem_status lmosem_inject_failure(lmosem_ctx *ctx);
+
+/* The plan a set iterates with: out4[0] events per forward tile, out4[1]
+ * waves of 64 emission pixels per forward workgroup (the pixel tile),
+ * out4[2] rows per backprojection chunk, out4[3] 1 if iterations replay a
+ * graph.  Errors: EINVAL. */
+lmosem_status lmosem_evset_plan(const lmosem_evset *set, int32_t *out4);
 
 /* Replay each global iteration of lmosem_iterate / lmosem_reconstruct as one
  * captured HIP graph (1, the default) or launch kernel by kernel (0); an

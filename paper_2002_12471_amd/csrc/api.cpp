@@ -22,6 +22,7 @@ struct lmosem_ctx {
     std::string err;
     bool poisoned = false;
     int ev_tile = 8;
+    int pixel_waves = 0;          // pixel tile of sets loaded from now on (waves of 64); 0: g.fwd_waves
     int *bad_dev = nullptr;
     unsigned long long *skipped_dev = nullptr;
     bool surrogate = false;        // scatter_model 2: network scatter term
@@ -69,10 +70,19 @@ struct lmosem_evset {
     float *col = nullptr;     // surrogate: per-sub-iteration event column features [max_rows][4] + ranks [max_rows][2]
     uint16_t *X = nullptr;    // surrogate: network inputs [pair_cap][8], bf16
     size_t pb_chunks = 0;     // chunk rows allocated in pb
+    size_t pmean_groups = 0;  // pixel groups allocated in pmean
     int64_t bytes = 0;        // device bytes held by the set (counted in its context's set_bytes)
 };
 
 namespace {
+
+// The context's geometry with the set's forward pixel tile (waves of 64
+// pixels per workgroup), which the autotuner may choose per set.
+Geo set_geo(const lmosem_ctx *c, const lmosem_evset *s) {
+    Geo g = c->g;
+    if (s && s->s.fwd_waves > 0) g.fwd_waves = s->s.fwd_waves;
+    return g;
+}
 
 constexpr int64_t kPairCap = 1 << 22;   // (event, pixel) pairs per surrogate network batch (64 MB of inputs)
 
@@ -169,7 +179,7 @@ void free_set(lmosem_evset *s) {
 
 // Device bytes a set holds with its current plan and workspace.
 int64_t set_device_bytes(const lmosem_ctx *c, const lmosem_evset *s) {
-    const Geo &g = c->g;
+    const Geo g = set_geo(c, s);
     const EvSet &v = s->s;
     const int64_t n = std::max<int64_t>(v.n, 1), rows = std::max(v.max_rows, 1);
     const int64_t chunks = std::max<int64_t>((int64_t)s->pb_chunks, 1);
@@ -177,7 +187,7 @@ int64_t set_device_bytes(const lmosem_ctx *c, const lmosem_evset *s) {
     const int64_t n_chunks = std::max<int64_t>(v.chunk_off.empty() ? 1 : v.chunk_off.back(), 1);
     int64_t b = 20 * n + (int64_t)sizeof(Tile) * n_tiles + (int64_t)sizeof(Chunk) * n_chunks +
                 8 * (int64_t)g.n_subsets * (v.n_real + 1);
-    b += 4 * rows * g.n_qpad + 4 * rows * forward_groups(g) + 8 * rows + 4 * chunks * g.n_qpad +
+    b += 4 * rows * g.n_qpad + 4 * rows * std::max<int64_t>((int64_t)s->pmean_groups, forward_groups(g)) + 8 * rows + 4 * chunks * g.n_qpad +
          4 * (int64_t)v.n_real * g.n_qpad + 8 * (int64_t)v.n_real;
     if (c->surrogate) b += 24 * rows + 8 * 2 * kPairCap;
     if (s->Hc) b += 4 * n * g.n_qpad;
@@ -186,12 +196,14 @@ int64_t set_device_bytes(const lmosem_ctx *c, const lmosem_evset *s) {
 
 // (Re)allocate the per-set workspace for the current tile plan.
 lmosem_status alloc_workspace(lmosem_ctx *c, lmosem_evset *s) {
-    const Geo &g = c->g;
+    const Geo g = set_geo(c, s);
     size_t rows = std::max(s->s.max_rows, 1), groups = forward_groups(g);
     size_t chunks = std::max(s->s.max_chunks, 1);
     hipError_t e;
 #define AL(p, bytes) do { if (!(p)) { e = hipMalloc(&(p), (bytes)); if (e != hipSuccess) return alloc_err(c, "workspace", e); } } while (0)
     AL(s->H, sizeof(float) * rows * g.n_qpad);
+    if (s->pmean && s->pmean_groups < groups) { hipFree(s->pmean); s->pmean = nullptr; }
+    if (!s->pmean) s->pmean_groups = groups;
     AL(s->pmean, sizeof(float) * rows * groups);
     AL(s->mean, sizeof(float) * rows);
     AL(s->inv, sizeof(float) * rows);
@@ -238,6 +250,7 @@ lmosem_status load_set(lmosem_ctx *c, const lmosem_events *ev, const lmosem_batc
     auto *s = new lmosem_evset();
     s->s.ctx = c;
     s->s.ev_tile = c->ev_tile;
+    s->s.fwd_waves = c->pixel_waves;
     std::string why;
     hipError_t e = sort_events(c->g, c->t, *ev, offs, force_subset, s->s, c->st, why);
     if (e != hipSuccess) {
@@ -308,7 +321,7 @@ hipError_t drain_timing(lmosem_ctx *c) {
 // System rows and partial means of subset i: exact forward projection, or
 // exact primaries plus the network's scatter term.
 hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStream_t st) {
-    const Geo &g = c->g;
+    const Geo g = set_geo(c, s);
     const EvSet &v = s->s;
     const int rows = v.row_off[i + 1] - v.row_off[i];
     if (c->surrogate) {
@@ -331,7 +344,7 @@ hipError_t forward_rows(lmosem_ctx *c, lmosem_evset *s, int i, float *H, hipStre
     });
 }
 
-int mean_groups(const lmosem_ctx *c) { return c->surrogate ? 1 : forward_groups(c->g); }
+int mean_groups(const lmosem_ctx *c, const lmosem_evset *s) { return c->surrogate ? 1 : forward_groups(set_geo(c, s)); }
 
 // One sub-iteration of Eq. 7 on all realisations of a prepared set: the
 // system rows are computed (and kept when the set caches them) or, once
@@ -343,7 +356,7 @@ hipError_t subiteration(lmosem_ctx *c, lmosem_evset *s, int i, bool want_ll, hip
     const int n_tiles = v.tile_off[i + 1] - v.tile_off[i];
     const int n_chunks = v.chunk_off[i + 1] - v.chunk_off[i];
     const bool cached = s->Hc && s->rows_valid;
-    const int groups = cached ? 1 : mean_groups(c);
+    const int groups = cached ? 1 : mean_groups(c, s);
     float *H = s->Hc ? s->Hc + (size_t)v.row_off[i] * g.n_qpad : s->H;
     const float *sens = c->t.sens + (size_t)i * g.n_qpad;
     const int *crange = v.crange + (size_t)i * (v.n_real + 1);
@@ -739,7 +752,7 @@ lmosem_status lmosem_forward(lmosem_ctx *c, const lmosem_events *ev, const float
     const int rows = v.row_off[1];
     hipError_t e = launch_gather_image(g, c->t, image_dev, 1, 0, s->f, 0, c->st);
     if (e == hipSuccess) e = forward_rows(c, s, 0, s->H, c->st);
-    if (e == hipSuccess) e = launch_mean(s->pmean, mean_groups(c), rows, s->mean, s->inv, c->skipped_dev, c->st);
+    if (e == hipSuccess) e = launch_mean(s->pmean, mean_groups(c, s), rows, s->mean, s->inv, c->skipped_dev, c->st);
     if (e == hipSuccess) e = launch_scatter_rows(s->mean, v.orig, rows, mean_dev, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e == hipSuccess) { c->terms += v.terms_sub[0]; c->useful += v.useful_sub[0]; }
@@ -803,6 +816,14 @@ lmosem_status lmosem_set_tuning(lmosem_ctx *c, int32_t event_tile) {
     if (event_tile != 8 && event_tile != 16 && event_tile != 32)
         return set_err(c, LMOSEM_EINVAL, "event_tile must be 8, 16 or 32");
     c->ev_tile = event_tile;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_set_pixel_tile(lmosem_ctx *c, int32_t pixels) {
+    GUARD(c);
+    if (pixels != 0 && pixels != 64 && pixels != 128 && pixels != 192 && pixels != 256)
+        return set_err(c, LMOSEM_EINVAL, "pixel tile must be 64, 128, 192 or 256 (0: the default)");
+    c->pixel_waves = pixels / 64;
     return LMOSEM_OK;
 }
 
@@ -1139,7 +1160,7 @@ std::string tune_key(const lmosem_ctx *c, const lmosem_evset *s) {
     return buf;
 }
 
-bool tune_lookup(const std::string &key, int &ev, int &ch, int &graph) {
+bool tune_lookup(const std::string &key, int &ev, int &ch, int &graph, int &waves) {
     const char *path = getenv("LMOSEM_TUNE_CACHE");
     if (!path) return false;
     FILE *fp = fopen(path, "r");
@@ -1150,17 +1171,21 @@ bool tune_lookup(const std::string &key, int &ev, int &ch, int &graph) {
         std::string l(line);
         size_t bar = l.find('|');
         if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-        found = sscanf(l.c_str() + bar + 1, "%d %d %d", &ev, &ch, &graph) == 3;
+        int w = 0;
+        const int got = sscanf(l.c_str() + bar + 1, "%d %d %d %d", &ev, &ch, &graph, &w);
+        found = got >= 3;
+        waves = got == 4 ? w : 0;   // lines without a pixel tile keep the context's
     }
     fclose(fp);
-    return found && (ev == 8 || ev == 16 || ev == 32) && ch >= 32 && (graph == 0 || graph == 1);
+    return found && (ev == 8 || ev == 16 || ev == 32) && ch >= 32 && (graph == 0 || graph == 1) && waves >= 0 &&
+           waves <= 4;
 }
 
-void tune_store(const std::string &key, int ev, int ch, int graph) {
+void tune_store(const std::string &key, int ev, int ch, int graph, int waves) {
     const char *path = getenv("LMOSEM_TUNE_CACHE");
     if (!path) return;
     if (FILE *fp = fopen(path, "a")) {
-        fprintf(fp, "%s|%d %d %d\n", key.c_str(), ev, ch, graph);
+        fprintf(fp, "%s|%d %d %d %d\n", key.c_str(), ev, ch, graph, waves);
         fclose(fp);
     }
 }
@@ -1204,30 +1229,45 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
         float *hc;
         ~Restore() { s->Hc = hc; s->rows_valid = false; drop_graphs(s); }
     } restore{s, hc};
-    int best_ev = v.ev_tile, best_ch = v.chunk_rows, best_graph = -1;
+    int best_ev = v.ev_tile, best_ch = v.chunk_rows, best_graph = -1, best_waves = v.fwd_waves;
     float fwd_ms = 0.0f;   // the fastest forward launch of the largest subset
     hipError_t e = hipSuccess;
-    if (!tune_lookup(key, best_ev, best_ch, best_graph)) {
+    if (tune_lookup(key, best_ev, best_ch, best_graph, best_waves)) {
+        v.fwd_waves = best_waves;
+    } else {
         best_graph = -1;
         // the largest subset is the one the choice matters for
         int big = 0;
         for (int i = 1; i < g.n_subsets; ++i)
             if (v.row_off[i + 1] - v.row_off[i] > v.row_off[big + 1] - v.row_off[big]) big = i;
         const int rows = v.row_off[big + 1] - v.row_off[big];
+        // events per tile x pixel tile (waves of 64 emission pixels per
+        // workgroup: 1, 2, 4 and the context's own choice, at most the
+        // emission set's waves)
+        std::vector<int> waves_opts;
+        for (int w : {1, 2, 4, g.fwd_waves})
+            if (w >= 1 && w <= std::min(4, g.n_qpad / 64) &&
+                std::find(waves_opts.begin(), waves_opts.end(), w) == waves_opts.end())
+                waves_opts.push_back(w);
         float best = 3.4e38f;
         for (int ev : {8, 16, 32}) {
-            if (c->surrogate) break;
+            if (c->surrogate || e != hipSuccess) break;
             if ((e = plan_tiles(g, c->t, v, ev, v.chunk_rows, c->st, why)) != hipSuccess) break;
-            lmosem_status ws = alloc_workspace(c, s);
-            if (ws != LMOSEM_OK) return ws;
-            float ms = 0.0f;
-            e = time_ms(c, [&] {
-                return launch_forward(ev, g, c->t, v.tiles + v.tile_off[big], v.tile_off[big + 1] - v.tile_off[big],
-                                      v.u, v.e, v.efac, s->f, s->H, s->pmean, v.row_off[big], rows, c->st);
-            }, ms);
-            if (e != hipSuccess) break;
-            if (ms < best) { best = ms; best_ev = ev; }
+            for (int w : waves_opts) {
+                v.fwd_waves = w;
+                lmosem_status ws = alloc_workspace(c, s);
+                if (ws != LMOSEM_OK) return ws;
+                const Geo gw = set_geo(c, s);
+                float ms = 0.0f;
+                e = time_ms(c, [&] {
+                    return launch_forward(ev, gw, c->t, v.tiles + v.tile_off[big], v.tile_off[big + 1] - v.tile_off[big],
+                                          v.u, v.e, v.efac, s->f, s->H, s->pmean, v.row_off[big], rows, c->st);
+                }, ms);
+                if (e != hipSuccess) break;
+                if (ms < best) { best = ms; best_ev = ev; best_waves = w; }
+            }
         }
+        if (!c->surrogate) v.fwd_waves = best_waves;
         fwd_ms = best < 3.4e38f ? best : 0.0f;
         best = 3.4e38f;
         for (int ch : {64, 128, 256, 512, 1024}) {
@@ -1264,7 +1304,7 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
     // iterations)
     if (best_graph < 0 && fwd_ms * g.n_subsets > 50.0f) {
         best_graph = 1;
-        tune_store(key, best_ev, best_ch, best_graph);
+        tune_store(key, best_ev, best_ch, best_graph, v.fwd_waves);
     }
     if (best_graph < 0) {
         // one full iteration launched directly versus replayed as a graph
@@ -1278,12 +1318,22 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
         if (e == hipSuccess) e = time_ms(c, [&] { return one_iteration(c, s, false); }, ms_graph);
         if (e != hipSuccess) return dev_err(c, "autotune", e);
         best_graph = ms_graph < ms_direct ? 1 : 0;
-        tune_store(key, best_ev, best_ch, best_graph);
+        tune_store(key, best_ev, best_ch, best_graph, v.fwd_waves);
     }
     s->use_graph = best_graph;
     if (event_tile) *event_tile = best_ev;
     if (chunk_rows) *chunk_rows = best_ch;
     if (use_graphs) *use_graphs = best_graph;
+    return LMOSEM_OK;
+}
+
+lmosem_status lmosem_evset_plan(const lmosem_evset *s, int32_t *out4) {
+    if (!s || !out4) return LMOSEM_EINVAL;
+    const lmosem_ctx *c = s->s.ctx;
+    out4[0] = s->s.ev_tile;
+    out4[1] = s->s.fwd_waves > 0 ? s->s.fwd_waves : c->g.fwd_waves;
+    out4[2] = s->s.chunk_rows;
+    out4[3] = s->use_graph >= 0 ? s->use_graph : (c->graphs ? 1 : 0);
     return LMOSEM_OK;
 }
 

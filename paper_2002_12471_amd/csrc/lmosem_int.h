@@ -219,6 +219,7 @@ struct EvSet {
     int n_real = 0;
     int64_t n = 0;
     int ev_tile = 8;
+    int fwd_waves = 0;      // waves per forward workgroup (the pixel tile, 64 pixels each); 0: the context's
     int chunk_rows = 256;   // rows per backprojection chunk
     std::vector<int> counts;   // events per (subset, realisation, angle) group
     // sorted SoA

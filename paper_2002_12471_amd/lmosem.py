@@ -85,11 +85,13 @@ _sigs = {
     "lmosem_events_free": (None, [_P]),
     "lmosem_iterate": (_S, [_P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
     "lmosem_set_tuning": (_S, [_P, ctypes.c_int32]),
+    "lmosem_set_pixel_tile": (_S, [_P, ctypes.c_int32]),
     "lmosem_get_stats": (_S, [_P, ctypes.POINTER(lmosem_stats)]),
     "lmosem_set_timing": (_S, [_P, ctypes.c_int32]),
     "lmosem_autotune": (_S, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_graphs": (_S, [_P, ctypes.c_int32]),
+    "lmosem_evset_plan": (_S, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lmosem_set_memory_cap": (_S, [_P, ctypes.c_int64]),
     "lmosem_memory_held": (_S, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "lmosem_inject_failure": (_S, [_P]),
@@ -270,6 +272,10 @@ def lmosem_set_tuning(ctx, event_tile: int):
     _check(ctx, _lib.lmosem_set_tuning(ctx, int(event_tile)))
 
 
+def lmosem_set_pixel_tile(ctx, pixels: int):
+    _check(ctx, _lib.lmosem_set_pixel_tile(ctx, int(pixels)))
+
+
 def lmosem_get_stats(ctx) -> dict:
     s = lmosem_stats()
     _check(ctx, _lib.lmosem_get_stats(ctx, ctypes.byref(s)))
@@ -287,6 +293,13 @@ def lmosem_autotune(ctx, evset) -> tuple:
     gr = ctypes.c_int32()
     _check(ctx, _lib.lmosem_autotune(ctx, evset, ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(gr)))
     return ev.value, ch.value, gr.value
+
+
+def lmosem_evset_plan(evset) -> dict:
+    """The set's plan: events per tile, pixel tile in waves of 64, chunk rows, graphs."""
+    out = (ctypes.c_int32 * 4)()
+    _check_plain(_lib.lmosem_evset_plan(evset, out), "lmosem_evset_plan")
+    return {"event_tile": out[0], "pixel_waves": out[1], "chunk_rows": out[2], "graphs": out[3]}
 
 
 def lmosem_set_graphs(ctx, enable: bool):
@@ -492,8 +505,9 @@ class Context:
         ll = lmosem_reconstruct(self.handle, events, n_iters, out, init, batch_offsets, want_loglik)
         return (out, ll) if want_loglik else out
 
-    def set_tuning(self, event_tile: int):
+    def set_tuning(self, event_tile: int, pixel_tile: int = 0):
         lmosem_set_tuning(self.handle, event_tile)
+        lmosem_set_pixel_tile(self.handle, pixel_tile)
 
     def stats(self) -> dict:
         return lmosem_get_stats(self.handle)

@@ -72,10 +72,12 @@ def test_forward_means_tiny(tiny, dev, which):
     assert np.max(_rel(got, ref)) <= 1e-4
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_event_tile_sizes_agree(tiny, dev, tile):
+@pytest.mark.parametrize("tile,pixels", [(8, 0), (16, 0), (32, 0), (8, 64), (32, 64), (16, 128), (8, 256)])
+def test_event_tile_sizes_agree(tiny, dev, tile, pixels):
+    # event tiles x pixel tiles (0: the default, the 192-pixel emission set in
+    # one workgroup; 256 leaves one wave of each workgroup idle)
     m, ctx, H = tiny["m"], tiny["ctx"], tiny["H"]
-    ctx.set_tuning(tile)
+    ctx.set_tuning(tile, pixels)
     try:
         img = torch.as_tensor(tiny["act"], device=dev)
         got = ctx.forward(tiny["evd"], img).cpu().numpy()
@@ -285,3 +287,44 @@ def test_autotune_keeps_results(tiny, dev):
         np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=2e-6, atol=1e-12)
     finally:
         L.lmosem_events_free(ev)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_pixel_tile_plans_match_oracle(brain, dev, tmp_path, monkeypatch, waves):
+    # the autotuner's first choice is stored in the tuning cache; the stored
+    # line is then rewritten to each pixel tile (64, 128, 256 emission pixels
+    # per forward workgroup), read back by the autotuner of a fresh set, and
+    # that plan's 10 iterations compared with the oracle
+    L, m, ctx, w = brain["L"], brain["m"], brain["ctx"], brain["w"]
+    ev = synth.workload_events(w, realisation=6, n_events=3000)
+    evd = L.events_to_device(ev, dev)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LMOSEM_TUNE_CACHE", str(cache))
+    first = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        tile, chunk, graphs = L.lmosem_autotune(ctx.handle, first)
+        plan = L.lmosem_evset_plan(first)
+        assert (plan["event_tile"], plan["chunk_rows"], plan["graphs"]) == (tile, chunk, graphs)
+        assert plan["pixel_waves"] in (1, 2, 4)
+    finally:
+        L.lmosem_events_free(first)
+    key, fields = cache.read_text().splitlines()[-1].split("|")
+    ev_tile, ch, gr, _ = (int(x) for x in fields.split())
+    cache.write_text(f"{key}|{ev_tile} {ch} {gr} {waves}\n")
+    evs = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        L.lmosem_autotune(ctx.handle, evs)
+        assert L.lmosem_evset_plan(evs) == {"event_tile": ev_tile, "pixel_waves": waves, "chunk_rows": ch,
+                                            "graphs": gr}
+        img = torch.as_tensor((brain["mu"] > 0).astype(np.float32), device=dev).contiguous()
+        L.lmosem_iterate(ctx.handle, evs, 10, img)
+        torch.cuda.synchronize()
+        got = img.cpu().numpy().ravel()[m.support]
+    finally:
+        L.lmosem_events_free(evs)
+    H = m.system_matrix(ev)
+    ns = brain["g"]["n_subsets"]
+    sens = np.stack([m.sensitivity(i) for i in range(ns)])
+    f_ref, _ = O.os_lm_mlem(H, ev["angle"], sens, 10, np.ones(len(m.support)), ns)
+    ok, worst = _image_ok(got, f_ref)
+    assert ok, worst
