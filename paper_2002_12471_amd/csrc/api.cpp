@@ -857,6 +857,11 @@ lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n,
     return net_forward(net->n, X_dev, n, y_dev, net_stream(net->n)) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
 }
 
+lmosem_status lmosem_net_forward_train(lmosem_net *net, const float *X_dev, int32_t n, float *y_dev) {
+    if (!net || !X_dev || !y_dev || n <= 0 || n % 16) return LMOSEM_EINVAL;
+    return net_forward_train(net->n, X_dev, n, y_dev) == hipSuccess ? LMOSEM_OK : LMOSEM_EDEVICE;
+}
+
 lmosem_status lmosem_net_gradient(lmosem_net *net, const float *X_dev, const float *dy_dev, int32_t n,
                                   float *grad_host) {
     if (!net || !X_dev || !dy_dev || !grad_host || n <= 0 || n % 16) return LMOSEM_EINVAL;

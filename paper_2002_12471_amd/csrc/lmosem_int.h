@@ -196,6 +196,7 @@ hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStrea
 // the packed weights of the fused inference kernel (mlp_infer.h)
 void net_fused_weights(const Net *n, const uint16_t **fw, const float **fb);
 hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host);
+hipError_t net_forward_train(Net *n, const float *X, int count, float *y);
 hipError_t net_train(Net *n, const float *X, const float *t, int64_t count, int batch, int epochs, float lr,
                      float lr_decay, double *loss_host);
 hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *C, int ldc, int M, int N,

@@ -310,26 +310,30 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // ---------------------------------------------------------------- fused inference
-// (the kernel: mlp_infer.h) packed weights: A operands in lane order, biases
-// and the output row
+// (the kernel: mlp_infer.h) packed weights: A operands in lane order (W1/4
+// in bf16; W2 and W3 rounded to bf16 as the training kernels use them, then
+// held in fp16, which represents those values exactly), the quartered biases
+// and the output row (bf16-rounded, widened)
+__device__ inline uint16_t f2h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+
 __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__ fw, float *__restrict__ fb) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < kFW1) {
         const int i = idx & 7, lane = (idx >> 3) & 63, ob = idx >> 9;
         const int in = perm_k(lane >> 4, i), out = 16 * ob + (lane & 15);
-        fw[idx] = in < kIn ? f2bf(p[kOffW1 + in * kHid + out]) : 0;
+        fw[idx] = in < kIn ? f2bf(kActScale * p[kOffW1 + in * kHid + out]) : 0;
     }
     if (idx < 2 * kFW2) {
         const int layer = idx / kFW2, r = idx % kFW2;
         const int i = r & 7, lane = (r >> 3) & 63, kb = (r >> 9) & 3, ob = r >> 11;
         const int in = 32 * kb + perm_k(lane >> 4, i), out = 16 * ob + (lane & 15);
-        fw[kFW1 + idx] = f2bf(p[(layer ? kOffW3 : kOffW2) + in * kHid + out]);
+        fw[kFW1 + idx] = f2h(bf2f(f2bf(p[(layer ? kOffW3 : kOffW2) + in * kHid + out])));
     }
     if (idx < kFB) {
         float v;
-        if (idx < kHid) v = p[kOffB1 + idx];
-        else if (idx < 2 * kHid) v = p[kOffB2 + idx - kHid];
-        else if (idx < 3 * kHid) v = p[kOffB3 + idx - 2 * kHid];
+        if (idx < kHid) v = kActScale * p[kOffB1 + idx];
+        else if (idx < 2 * kHid) v = kActScale * p[kOffB2 + idx - kHid];
+        else if (idx < 3 * kHid) v = kActScale * p[kOffB3 + idx - 2 * kHid];
         else if (idx < 4 * kHid) v = bf2f(f2bf(p[kOffW4 + idx - 3 * kHid]));
         else v = p[kOffB4];
         fb[idx] = v;
@@ -501,6 +505,12 @@ hipError_t net_forward(Net *n, const float *X, int64_t count, float *y, hipStrea
     hipLaunchKernelGGL(k_mlp_infer<XSource>, dim3(grid), dim3(kFusedThreads), 0, st, n->fw, n->fb,
                        XSource{X, y}, count);
     return hipGetLastError();
+}
+
+hipError_t net_forward_train(Net *n, const float *X, int count, float *y) {
+    if (count <= 0 || count % 16) return hipErrorInvalidValue;
+    hipError_t e = ensure_ws(*n, count);
+    return e == hipSuccess ? forward_batch(*n, X, count, y, false) : e;
 }
 
 hipError_t net_gradient(Net *n, const float *X, const float *dy, int count, float *grad_host) {

@@ -1,5 +1,7 @@
 // The fused inference kernel of the scatter-surrogate network (8 -> 128 ->
-// 128 -> 128 -> 1, GELU in its tanh form, bf16 MFMA with FP32 accumulation),
+// 128 -> 128 -> 1, GELU in its tanh form, MFMA with FP32 accumulation: bf16
+// inputs and weights, the later layers' weights held in fp16 (exactly) so
+// that they multiply fp16 activations),
 // as a template over where its inputs come from and where its outputs go:
 // a sample array (lmosem_net_forward) or the (event, pixel) pairs of a
 // learned-scatter sub-iteration, whose inputs are formed in the kernel.
@@ -31,8 +33,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // which bounds the kernel).  The weights, pre-permuted into A-operand lane
 // order, the biases and the output row sit in LDS (80 KB), shared by the
 // sixteen waves of one workgroup per CU; each wave takes 32 samples per step
-// (123 VGPRs, four waves per SIMD).
+// (126 VGPRs, four waves per SIMD).
+//
+// Every hidden pre-activation is carried at a quarter of its value, s = z/4
+// (layer 1 has W1/4 and b1/4; every layer's biases are quartered), and each
+// layer stores g = gelu(4 s)/4, so that the next layer's products with the
+// plain weights give the next s; the output is 4 (W4 . g3) + b4.  Powers of
+// two scale exactly, so this is the unscaled network with its activations
+// rounded to fp16.  With s in [-1, 1] mapped to w = s^2 in [0, 1], the GELU's
+// sigmoid factor is a polynomial in packed fp16 arithmetic, two activations
+// per instruction and no transcendental (the clamp modifiers saturate it to
+// 0 or 1 beyond |z| = 4, where the tanh form is within 7e-5 of that).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
 constexpr int kFW2 = 8 * 4 * 64 * 8;             // hidden layers [ob][kb][lane][8]
 constexpr int kFWTotal = kFW1 + 2 * kFW2;        // bf16 elements
@@ -41,16 +56,56 @@ constexpr int kFusedNB = 2;                      // 16-sample column blocks per 
 constexpr int kFusedWaves = 16;                  // one workgroup per CU: 4 waves per SIMD share one LDS copy
 constexpr int kFusedThreads = 64 * kFusedWaves;
 constexpr int kFusedTile = kFusedWaves * 16 * kFusedNB;   // samples per workgroup step
-// gelu(z) = z sigmoid(2u), u = sqrt(2/pi) (z + 0.044715 z^3): the tanh form
-// rewritten with one exp2 and one reciprocal
-constexpr float kGeluK0 = 2.0f * 0.7978845608028654f * 1.4426950408889634f;
-constexpr float kGeluK1 = kGeluK0 * 0.044715f;
+constexpr float kActScale = 0.25f;               // s = z / 4
 
 __device__ __host__ inline int perm_k(int g, int i) { return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4); }
 
-__device__ inline float gelu_fast(float z) {
-    const float t = z * fmaf(kGeluK1, z * z, kGeluK0);
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-t));
+__device__ inline f16x2 clamp01(f16x2 x) {
+    return __builtin_elementwise_min(__builtin_elementwise_max(x, f16x2{0, 0}), f16x2{1, 1});
+}
+
+// g = gelu(4 s) / 4 for quarter-scale pre-activations, N pairs side by side
+// (independent chains, interleaved step by step).  The sigmoid factor of the
+// tanh form, sigma(2 sqrt(2/pi) (z + 0.044715 z^3)) at z = 4 s, is
+// 1/2 + s P(s^2 - 1/2), P of degree 6 with fp16 coefficients fitted
+// (weighted least squares on |s| times the error, each coefficient rounded
+// to fp16 before the lower ones are refitted) on |s| <= 1: the result is
+// within 5e-4 of gelu(4 s)/4, fp16 arithmetic included.
+template <int N>
+__device__ inline void gelu_quarter(f16x2 (&s)[N]) {
+    constexpr _Float16 c[7] = {0.7041015625f16, -0.67626953125f16, 0.88525390625f16, -1.1181640625f16,
+                               1.5205078125f16, -2.162109375f16,   1.6064453125f16};
+    f16x2 t[N], q[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = clamp01(s[i] * s[i]) - f16x2{0.5f16, 0.5f16};
+#pragma unroll
+    for (int i = 0; i < N; ++i) q[i] = __builtin_elementwise_fma(f16x2{c[6], c[6]}, t[i], f16x2{c[5], c[5]});
+#pragma unroll
+    for (int k = 4; k >= 0; --k)
+#pragma unroll
+        for (int i = 0; i < N; ++i) q[i] = __builtin_elementwise_fma(q[i], t[i], f16x2{c[k], c[k]});
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = s[i] * clamp01(__builtin_elementwise_fma(s[i], q[i], f16x2{0.5f16, 0.5f16}));
+}
+
+// the activations of one 16-row output block of each column block (four
+// FP32 accumulators of one sample each) as elements 4h .. 4h+3 of the
+// next layer's B operands
+__device__ inline void gelu_block(const f32x4 (&acc)[kFusedNB], f16x8 (&dst)[kFusedNB], int h) {
+    f16x2 v[2 * kFusedNB];
+#pragma unroll
+    for (int nb = 0; nb < kFusedNB; ++nb) {
+        v[2 * nb] = __builtin_convertvector(f32x2{acc[nb][0], acc[nb][1]}, f16x2);
+        v[2 * nb + 1] = __builtin_convertvector(f32x2{acc[nb][2], acc[nb][3]}, f16x2);
+    }
+    gelu_quarter(v);
+#pragma unroll
+    for (int nb = 0; nb < kFusedNB; ++nb) {
+        dst[nb][4 * h + 0] = v[2 * nb][0];
+        dst[nb][4 * h + 1] = v[2 * nb][1];
+        dst[nb][4 * h + 2] = v[2 * nb + 1][0];
+        dst[nb][4 * h + 3] = v[2 * nb + 1][1];
+    }
 }
 
 // bias-initialised accumulators of output block ob for this lane's rows
@@ -59,9 +114,9 @@ __device__ inline f32x4 bias4(const float *b, int ob, int g) {
 }
 
 // one 128 -> 128 layer with GELU, activations in and out as B operands
-__device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
-                                    bf16x8 (&act)[4][kFusedNB]) {
-    bf16x8 nxt[4][kFusedNB];
+__device__ inline void hidden_layer(const f16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
+                                    f16x8 (&act)[4][kFusedNB]) {
+    f16x8 nxt[4][kFusedNB];
 #pragma unroll
     for (int ob = 0; ob < 8; ++ob) {
         f32x4 acc[kFusedNB];
@@ -70,15 +125,12 @@ __device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *_
         for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = bv;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-            const bf16x8 a = w[(ob * 4 + kb) * 64 + lane];
+            const f16x8 a = w[(ob * 4 + kb) * 64 + lane];
 #pragma unroll
             for (int nb = 0; nb < kFusedNB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, act[kb][nb], acc[nb], 0, 0, 0);
         }
-#pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[nb][v]);
+        gelu_block(acc, nxt[ob >> 1], ob & 1);
     }
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
@@ -91,7 +143,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
                                                              const float *__restrict__ fb, Src src, int64_t n) {
     __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
     __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
-    __shared__ __attribute__((aligned(16))) __bf16 s_w4[4 * 64 * 8];
+    __shared__ __attribute__((aligned(16))) _Float16 s_w4[4 * 64 * 8];
     {
         const uint4 *w_src = reinterpret_cast<const uint4 *>(fw);
         uint4 *dst = reinterpret_cast<uint4 *>(s_w);
@@ -99,18 +151,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
         for (int i = threadIdx.x; i < kFB; i += kFusedThreads) s_b[i] = fb[i];
         // the output row as the A operand of an MFMA whose first row is W4
         // (every other row zero), k-blocks permuted as the hidden layers' are;
-        // the stored W4 values are bf16 already
+        // the stored W4 values are fp16 already
         for (int i = threadIdx.x; i < 4 * 64 * 8; i += kFusedThreads) {
             const int kb = i >> 9, l = (i >> 3) & 63, e = i & 7;
-            s_w4[i] = (l & 15) == 0 ? (__bf16)fb[3 * kHid + 32 * kb + perm_k(l >> 4, e)] : (__bf16)0.0f;
+            s_w4[i] = (l & 15) == 0 ? (_Float16)fb[3 * kHid + 32 * kb + perm_k(l >> 4, e)] : (_Float16)0.0f;
         }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
-    const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
-    const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
+    const f16x8 *w2 = reinterpret_cast<const f16x8 *>(s_w + kFW1);
+    const f16x8 *w3 = reinterpret_cast<const f16x8 *>(s_w + kFW1 + kFW2);
     const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         // keep the weight reads inside the loop (hoisting them would need
@@ -119,52 +171,43 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
         const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
         // layer 1: the inputs as B operands (lane groups 0 and 1 hold
         // features 0..3 and 4..7; every other slot is zero)
-        bf16x8 act[4][kFusedNB];
+        bf16x8 xin[kFusedNB];
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) {
             const int64_t p = base + 16 * nb + r;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (g < 2 && p < n) v = src.inputs(p, g);
-            const bf16x8 xin = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
-                                (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-            act[0][nb] = xin;
+            xin[nb] = bf16x8{(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
+                             (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
         }
-        {
-            bf16x8 nxt[4][kFusedNB];
+        f16x8 act[4][kFusedNB];
 #pragma unroll
-            for (int ob = 0; ob < 8; ++ob) {
-                const bf16x8 a = w1[ob * 64 + lane];
-                const f32x4 bv = bias4(s_b, ob, g);
+        for (int ob = 0; ob < 8; ++ob) {
+            const bf16x8 a = w1[ob * 64 + lane];
+            const f32x4 bv = bias4(s_b, ob, g);
+            f32x4 acc[kFusedNB];
 #pragma unroll
-                for (int nb = 0; nb < kFusedNB; ++nb) {
-                    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[0][nb], bv, 0, 0, 0);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) nxt[ob >> 1][nb][(ob & 1) * 4 + v] = (__bf16)gelu_fast(acc[v]);
-                }
-            }
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-                for (int nb = 0; nb < kFusedNB; ++nb) act[kb][nb] = nxt[kb][nb];
+            for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[nb], bv, 0, 0, 0);
+            gelu_block(acc, act[ob >> 1], ob & 1);
         }
         hidden_layer(w2, s_b + kHid, lane, g, act);
         hidden_layer(w3, s_b + 2 * kHid, lane, g, act);
         // output row on the MFMA: row 0 of the product holds y, in register 0
         // of lanes 0-15 (sample r of each 16-sample block)
-        const bf16x8 *w4 = reinterpret_cast<const bf16x8 *>(s_w4);
+        const f16x8 *w4 = reinterpret_cast<const f16x8 *>(s_w4);
         f32x4 o[kFusedNB];
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-            const bf16x8 a = w4[kb * 64 + lane];
+            const f16x8 a = w4[kb * 64 + lane];
 #pragma unroll
-            for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], o[nb], 0, 0, 0);
+            for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, act[kb][nb], o[nb], 0, 0, 0);
         }
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) {
             const int64_t p = base + 16 * nb + r;
-            if (g == 0 && p < n) src.output(p, o[nb][0] + s_b[4 * kHid]);
+            if (g == 0 && p < n) src.output(p, fmaf(1.0f / kActScale, o[nb][0], s_b[4 * kHid]));
         }
     }
 }

@@ -105,6 +105,7 @@ _sigs = {
     "lmosem_net_get_params": (_S, [_P, _P]),
     "lmosem_net_forward": (_S, [_P, _P, ctypes.c_int64, _P]),
     "lmosem_net_gradient": (_S, [_P, _P, _P, ctypes.c_int32, _P]),
+    "lmosem_net_forward_train": (_S, [_P, _P, ctypes.c_int32, _P]),
     "lmosem_net_train": (_S, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                               ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
     "lmosem_surrogate_samples": (_S, [_P, _P, _P, _P, _P, ctypes.c_int64, _P, _P, _P]),
@@ -415,6 +416,11 @@ def lmosem_net_get_params(net) -> dict:
 def lmosem_net_forward(net, X: torch.Tensor, y_out: torch.Tensor):
     _check_plain(_lib.lmosem_net_forward(net, _dev_ptr(X, torch.float32, "X"), int(X.shape[0]),
                                          _dev_ptr(y_out, torch.float32, "y")), "lmosem_net_forward")
+
+
+def lmosem_net_forward_train(net, X: torch.Tensor, y_out: torch.Tensor):
+    _check_plain(_lib.lmosem_net_forward_train(net, _dev_ptr(X, torch.float32, "X"), int(X.shape[0]),
+                                               _dev_ptr(y_out, torch.float32, "y")), "lmosem_net_forward_train")
 
 
 def lmosem_net_gradient(net, X: torch.Tensor, dy: torch.Tensor) -> dict:

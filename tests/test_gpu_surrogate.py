@@ -46,9 +46,30 @@ def test_network_forward_matches_reference(dev):
         y = torch.empty(1000, device=dev)
         L.lmosem_net_forward(net, torch.as_tensor(X, device=dev), y)
         torch.cuda.synchronize()
+        ref, _ = M.forward(p, X, rounding="infer")
+        got = y.cpu().numpy()
+        print(f"max |y - ref| {np.max(np.abs(got - ref)):.2e}, max |ref| {np.max(np.abs(ref)):.2f}")
+        assert np.max(np.abs(got - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+    finally:
+        L.lmosem_net_destroy(net)
+
+
+def test_training_forward_matches_reference(dev):
+    # the training kernels' forward pass (bf16 throughout)
+    L = _lib()
+    p = _params(6)
+    X = np.random.default_rng(2).normal(size=(1024, 8)).astype(np.float32)
+    net = L.lmosem_net_create(p)
+    try:
+        y = torch.empty(1024, device=dev)
+        L.lmosem_net_forward_train(net, torch.as_tensor(X, device=dev), y)
+        torch.cuda.synchronize()
         ref, _ = M.forward(p, X, bf16_round=True)
         got = y.cpu().numpy()
+        print(f"max |y - ref| {np.max(np.abs(got - ref)):.2e}, max |ref| {np.max(np.abs(ref)):.2f}")
         assert np.max(np.abs(got - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+        with pytest.raises(L.LmosemError):
+            L.lmosem_net_forward_train(net, torch.as_tensor(X[:1000], device=dev), y[:1000])
     finally:
         L.lmosem_net_destroy(net)
 
@@ -71,7 +92,8 @@ def test_network_forward_every_workgroup_loops(dev):
     finally:
         L.lmosem_net_destroy(net)
     idx = np.concatenate([np.sort(rng.choice(n - 37, 4000, replace=False)), np.arange(n - 37, n)])
-    ref, _ = M.forward(p, X[idx], bf16_round=True)
+    ref, _ = M.forward(p, X[idx], rounding="infer")
+    print(f"max |y - ref| {np.max(np.abs(got[idx] - ref)):.2e}, max |ref| {np.max(np.abs(ref)):.2f}")
     assert np.max(np.abs(got[idx] - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
 
 
@@ -115,7 +137,7 @@ def test_adam_step_matches_reference(dev):
     try:
         Xd, td = torch.as_tensor(X, device=dev), torch.as_tensor(t, device=dev)
         y = torch.empty(128, device=dev)
-        L.lmosem_net_forward(net, Xd, y)
+        L.lmosem_net_forward_train(net, Xd, y)   # the outputs the training step's loss uses
         dy = (2.0 * (y - td) / 128).contiguous()
         g = L.lmosem_net_gradient(net, Xd, dy)
         L.lmosem_net_train(net, Xd, td, batch=128, epochs=1, lr=1e-3)
@@ -317,7 +339,7 @@ def test_far_field_composition_matches_oracle(dev):
                 far_feats.append(O.surrogate_features(m1, int(pix), a, u, e))
                 far_ev.append(j)
                 far_f.append(float(act.flat[pix]))
-    y, _ = M.forward(p, np.array(far_feats), bf16_round=True)
+    y, _ = M.forward(p, np.array(far_feats), rounding="infer")
     term = np.array(far_f) * s0 * np.maximum(np.exp(y) - 1e-4, 0.0)
     far = np.bincount(far_ev, weights=term, minlength=len(got))
     slack = np.bincount(far_ev, weights=2e-3 * np.maximum(1.0, np.abs(y)) * term, minlength=len(got))
