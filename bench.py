@@ -135,14 +135,14 @@ def cpu_baseline(w, act, mu, ev, n_sample=2048, seed=11):
 
 
 # The fused network per (event, pixel) pair: 384 GELUs evaluated two at a
-# time in packed fp16 arithmetic, eleven instructions per pair of them (the
-# conversion from the FP32 accumulators, the polynomial and the clamps; no
-# transcendental): 2,112 lane-ops.  Packed fp16 instructions issue at 64
-# lanes per CU and clock (measured 56-62; no dual issue), 33 CU-clocks per
-# pair.  The MFMA work (67,840 useful flops per pair, the output row
+# time, thirteen instructions per pair of them (the conversion from the FP32
+# accumulators, the sigmoid factor's polynomial and clamps in packed fp16, two
+# mixed-precision products and the bf16 rounding; no transcendental): 2,496
+# lane-ops.  These issue at 64 lanes per CU and clock (packed fp16 measured
+# at 56-62; no dual issue), 39 CU-clocks per pair.  The MFMA work (67,840 useful flops per pair, the output row
 # included; 77,824 as issued, with layer 1's inputs padded to 32 and the
 # output row's fifteen zero rows) takes 19.1 CU-clocks at 2.5 PFLOP/s.
-MLP_PK_OPS, MLP_PK_LANES = 192 * 11, 64
+MLP_PK_OPS, MLP_PK_LANES = 192 * 13, 64
 MLP_PEAK_PAIRS = N_CU * CLK / (MLP_PK_OPS / MLP_PK_LANES)
 MLP_FLOPS_PER_PAIR = 2 * (8 * 128 + 2 * 128 * 128 + 128)
 BF16_PEAK_FLOPS = 2.5e15   # MI355X dense bf16 MFMA
@@ -296,8 +296,7 @@ def surrogate_compare(L, torch, np, synth, large, epochs, steps, warm, full):
     target = ("the 128x128 brain (2M events, 16 subsets; event errors on a seeded 64k subsample)" if large
               else "the tiny disk (5000 events, 1 subset)")
     out = {
-        "workload": f"MLP 8-128-128-128-1 GELU, MFMA with FP32 accumulation (bf16 inputs and weights, fp16 "
-                    f"activations), trained on {train['samples']} "
+        "workload": f"MLP 8-128-128-128-1 GELU, bf16 MFMA with FP32 accumulation, trained on {train['samples']} "
                     f"far-field samples from {train['maps']} random elliptical maps (mu 0.1-0.3/cm, {train['grid']}), "
                     f"near field exact, used in LM-OSEM on {target}",
         "events": J, "support_pixels": n_sup, "eval_events": int(len(idx)), "steps": steps, "warmup": warm,
@@ -310,8 +309,8 @@ def surrogate_compare(L, torch, np, synth, large, epochs, steps, warm, full):
         "network_roofline": {
             "bound": "alu", "kernel": "k_mlp_infer", "achieved": pairs_live / 1e9, "peak": peak_pairs / 1e9,
             "unit": "Gpair/s", "frac": pairs_live / peak_pairs,
-            "per_unit": f"one (event, emission pixel) pair = {MLP_PK_OPS} packed-fp16 VALU lane-ops "
-                        f"(384 GELUs) at {MLP_PK_LANES} lanes/clk/CU",
+            "per_unit": f"one (event, emission pixel) pair = {MLP_PK_OPS} VALU lane-ops for its 384 GELUs "
+                        f"(packed fp16 polynomial, bf16 result) at {MLP_PK_LANES} lanes/clk/CU",
             "frac_published_bf16": pairs_live * MLP_FLOPS_PER_PAIR / BF16_PEAK_FLOPS,
             "units_per_launch": net_stats["network_pairs"] / max(1, net_stats["network_launches"]),
             "avg_launch_us": net_stats["network_ms"] * 1e3 / max(1, net_stats["network_launches"]),
@@ -331,7 +330,7 @@ def bench_surrogate(args, L, torch, np, synth):
     out = {
         "metric": METRIC, "value": r["surrogate_events_per_s"], "unit": "events/s", "n_gpus": 1,
         "steps": steps, "warmup": warm, "ms_per_step": r["events"] / r["surrogate_events_per_s"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f16+f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32",
         "data": "synthetic (Monte-Carlo list-mode events; random elliptical training maps)",
         "config": {"workload": f"{args.workload}: {r['workload']}", "events": r["events"],
                    "support_pixels": r["support_pixels"]},

@@ -385,8 +385,8 @@ lmosem_status lmosem_measure_alu_rates(void *hip_stream, double *out3);
  * (|u - u_q| >= 3 sigma_u).  Inside it (the near field) the scatter sum is
  * exact, from a table of the path ends within 6 sigma_u of u_q, and the
  * primary term is always exact.  Network: 8 -> 128 -> 128 -> 128 -> 1, GELU
- * (tanh form), bf16 weights, 16-bit activations (bf16 in training, fp16 in
- * inference) with FP32 accumulation on MFMA, FP32 master weights, Adam.  Inputs x (8 floats per pair: offset from q's
+ * (tanh form), bf16 weights and activations with FP32 accumulation on MFMA,
+ * FP32 master weights, Adam.  Inputs x (8 floats per pair: offset from q's
  * detector position, energy, where the event's detector line enters and
  * leaves the body relative to q's depth, that line's response-weighted
  * attenuation, attenuation from q toward and away from the detector, mu at
@@ -403,10 +403,11 @@ void lmosem_net_destroy(lmosem_net *net);
 /* Current FP32 master parameters into params_host[34305] (synchronises). */
 lmosem_status lmosem_net_get_params(lmosem_net *net, float *params_host);
 /* y_dev[n] = network(X_dev[n][8]), on the network's stream; one fused kernel
- * (all four layers, weights in LDS) with bf16 inputs and weights (as in
- * training), fp16 activations (GELU as a polynomial in fp16 arithmetic,
- * within 2e-3 of the tanh form) and FP32 accumulation; the learned-scatter
- * rows use the same kernel. */
+ * (all four layers, weights in LDS) with bf16 inputs, weights and
+ * activations and FP32 accumulation, as in training; its GELU's sigmoid
+ * factor is a polynomial evaluated in fp16 arithmetic (within 2e-3 of the
+ * tanh form), the activation rounded to bf16.  The learned-scatter rows use
+ * the same kernel. */
 lmosem_status lmosem_net_forward(lmosem_net *net, const float *X_dev, int64_t n, float *y_dev);
 /* y_dev[n] from the training kernels' forward pass (bf16 inputs, weights and
  * activations, FP32 accumulation): the outputs that lmosem_net_train's loss

@@ -7,13 +7,9 @@ mean-squared-error loss, and Adam with bias correction (Kingma and Ba,
 "Adam: a method for stochastic optimization", ICLR 2015).
 
 With ``bf16_round=True`` the passes round to bfloat16 (round to nearest
-even) exactly where the GPU training kernels do: the inputs and weights of
-every matrix product, the activations fed to the next product and, backward,
-the layer deltas.  ``rounding="infer"`` rounds where the GPU inference kernel
-does: the inputs and every weight to bfloat16 (as in training), and every
-hidden pre-activation and activation to IEEE half precision (fp16, nearest
-even).  (The kernel's GELU is a polynomial
-approximation of the same function; that is not modelled here.)
+even) exactly where the GPU kernels do: the inputs and weights of every
+matrix product, the activations fed to the next product and, backward, the
+layer deltas.
 """
 from __future__ import annotations
 
@@ -32,11 +28,6 @@ def bf16(x) -> np.ndarray:
     return (b.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
-def fp16(x) -> np.ndarray:
-    """Round to IEEE binary16 (nearest, ties to even); returns float64."""
-    return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
-
-
 def gelu(x):
     return 0.5 * x * (1.0 + np.tanh(C_GELU * (x + A_GELU * x ** 3)))
 
@@ -52,27 +43,21 @@ def _w(p, k, rnd):
     return bf16(w) if rnd else w
 
 
-def forward(p: dict, X: np.ndarray, bf16_round: bool = False, rounding: str | None = None):
+def forward(p: dict, X: np.ndarray, bf16_round: bool = False):
     """y = W4^T gelu(W3^T gelu(W2^T gelu(W1^T x + b1) + b2) + b3) + b4 per row of X.
-    ``rounding``: None, "bf16" (the same as ``bf16_round=True``) or "infer".
     Returns (y, cache)."""
-    rnd = rounding or ("bf16" if bf16_round else None)
-    assert rnd in (None, "bf16", "infer")
     h = np.asarray(X, np.float64)
-    if rnd:
+    if bf16_round:
         h = bf16(h)
     cache = {"h0": h}
     for i in range(1, LAYERS):
-        z = h @ _w(p, f"W{i}", rnd) + np.asarray(p[f"b{i}"], np.float64)
-        if rnd == "infer":
-            h = fp16(gelu(fp16(z)))
-        else:
-            h = gelu(z)
-            if rnd:
-                h = bf16(h)
+        z = h @ _w(p, f"W{i}", bf16_round) + np.asarray(p[f"b{i}"], np.float64)
+        h = gelu(z)
+        if bf16_round:
+            h = bf16(h)
         cache[f"z{i}"] = z
         cache[f"h{i}"] = h
-    y = h @ _w(p, "W4", rnd)[:, 0] + float(p["b4"][0])
+    y = h @ _w(p, "W4", bf16_round)[:, 0] + float(p["b4"][0])
     return y, cache
 
 

@@ -310,11 +310,9 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // ---------------------------------------------------------------- fused inference
-// (the kernel: mlp_infer.h) packed weights: A operands in lane order (W1/4
-// in bf16; W2 and W3 rounded to bf16 as the training kernels use them, then
-// held in fp16, which represents those values exactly), the quartered biases
-// and the output row (bf16-rounded, widened)
-__device__ inline uint16_t f2h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+// (the kernel: mlp_infer.h) packed weights: A operands in lane order (W1/4,
+// W2 and W3 in bf16), the quartered biases and the output row (bf16-rounded,
+// widened)
 
 __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__ fw, float *__restrict__ fb) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +325,7 @@ __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__
         const int layer = idx / kFW2, r = idx % kFW2;
         const int i = r & 7, lane = (r >> 3) & 63, kb = (r >> 9) & 3, ob = r >> 11;
         const int in = 32 * kb + perm_k(lane >> 4, i), out = 16 * ob + (lane & 15);
-        fw[kFW1 + idx] = f2h(bf2f(f2bf(p[(layer ? kOffW3 : kOffW2) + in * kHid + out])));
+        fw[kFW1 + idx] = f2bf(p[(layer ? kOffW3 : kOffW2) + in * kHid + out]);
     }
     if (idx < kFB) {
         float v;

@@ -1,7 +1,5 @@
 // The fused inference kernel of the scatter-surrogate network (8 -> 128 ->
-// 128 -> 128 -> 1, GELU in its tanh form, MFMA with FP32 accumulation: bf16
-// inputs and weights, the later layers' weights held in fp16 (exactly) so
-// that they multiply fp16 activations),
+// 128 -> 128 -> 1, GELU in its tanh form, bf16 MFMA with FP32 accumulation),
 // as a template over where its inputs come from and where its outputs go:
 // a sample array (lmosem_net_forward) or the (event, pixel) pairs of a
 // learned-scatter sub-iteration, whose inputs are formed in the kernel.
@@ -39,13 +37,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // (layer 1 has W1/4 and b1/4; every layer's biases are quartered), and each
 // layer stores g = gelu(4 s)/4, so that the next layer's products with the
 // plain weights give the next s; the output is 4 (W4 . g3) + b4.  Powers of
-// two scale exactly, so this is the unscaled network with its activations
-// rounded to fp16.  With s in [-1, 1] mapped to w = s^2 in [0, 1], the GELU's
-// sigmoid factor is a polynomial in packed fp16 arithmetic, two activations
-// per instruction and no transcendental (the clamp modifiers saturate it to
-// 0 or 1 beyond |z| = 4, where the tanh form is within 7e-5 of that).
+// two scale exactly in bf16, so this is the unscaled network with its
+// activations rounded to bf16.  With s in [-1, 1] mapped to w = s^2 in
+// [0, 1], the GELU's sigmoid factor is a polynomial in packed fp16
+// arithmetic, two activations per instruction and no transcendental (the
+// clamp modifiers saturate it to 0 or 1 beyond |z| = 4, where the tanh form
+// is within 7e-5 of that); the product s times that factor is formed in FP32
+// from the two fp16 values and rounded once, to bf16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 constexpr int kFW1 = 8 * 64 * 8;                 // layer 1 A operands [ob][lane][8]
@@ -64,15 +64,15 @@ __device__ inline f16x2 clamp01(f16x2 x) {
     return __builtin_elementwise_min(__builtin_elementwise_max(x, f16x2{0, 0}), f16x2{1, 1});
 }
 
-// g = gelu(4 s) / 4 for quarter-scale pre-activations, N pairs side by side
-// (independent chains, interleaved step by step).  The sigmoid factor of the
+// The GELU's sigmoid factor for quarter-scale pre-activations, N pairs side
+// by side (independent chains, interleaved step by step): the factor of the
 // tanh form, sigma(2 sqrt(2/pi) (z + 0.044715 z^3)) at z = 4 s, is
 // 1/2 + s P(s^2 - 1/2), P of degree 6 with fp16 coefficients fitted
 // (weighted least squares on |s| times the error, each coefficient rounded
-// to fp16 before the lower ones are refitted) on |s| <= 1: the result is
+// to fp16 before the lower ones are refitted) on |s| <= 1: s times it is
 // within 5e-4 of gelu(4 s)/4, fp16 arithmetic included.
 template <int N>
-__device__ inline void gelu_quarter(f16x2 (&s)[N]) {
+__device__ inline void gelu_factor(const f16x2 (&s)[N], f16x2 (&S)[N]) {
     constexpr _Float16 c[7] = {0.7041015625f16, -0.67626953125f16, 0.88525390625f16, -1.1181640625f16,
                                1.5205078125f16, -2.162109375f16,   1.6064453125f16};
     f16x2 t[N], q[N];
@@ -85,26 +85,35 @@ __device__ inline void gelu_quarter(f16x2 (&s)[N]) {
 #pragma unroll
         for (int i = 0; i < N; ++i) q[i] = __builtin_elementwise_fma(q[i], t[i], f16x2{c[k], c[k]});
 #pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = s[i] * clamp01(__builtin_elementwise_fma(s[i], q[i], f16x2{0.5f16, 0.5f16}));
+    for (int i = 0; i < N; ++i) S[i] = clamp01(__builtin_elementwise_fma(s[i], q[i], f16x2{0.5f16, 0.5f16}));
+}
+
+// g = s S(s) in FP32 from fp16 s and S (one mixed-precision FMA each),
+// two of them rounded to bf16 together
+__device__ inline bf16x2 gelu_out(f16x2 s, f16x2 S) {
+    return __builtin_convertvector(f32x2{__builtin_fmaf((float)S[0], (float)s[0], 0.0f),
+                                         __builtin_fmaf((float)S[1], (float)s[1], 0.0f)},
+                                   bf16x2);
 }
 
 // the activations of one 16-row output block of each column block (four
 // FP32 accumulators of one sample each) as elements 4h .. 4h+3 of the
 // next layer's B operands
-__device__ inline void gelu_block(const f32x4 (&acc)[kFusedNB], f16x8 (&dst)[kFusedNB], int h) {
-    f16x2 v[2 * kFusedNB];
+__device__ inline void gelu_block(const f32x4 (&acc)[kFusedNB], bf16x8 (&dst)[kFusedNB], int h) {
+    f16x2 v[2 * kFusedNB], S[2 * kFusedNB];
 #pragma unroll
     for (int nb = 0; nb < kFusedNB; ++nb) {
         v[2 * nb] = __builtin_convertvector(f32x2{acc[nb][0], acc[nb][1]}, f16x2);
         v[2 * nb + 1] = __builtin_convertvector(f32x2{acc[nb][2], acc[nb][3]}, f16x2);
     }
-    gelu_quarter(v);
+    gelu_factor(v, S);
 #pragma unroll
     for (int nb = 0; nb < kFusedNB; ++nb) {
-        dst[nb][4 * h + 0] = v[2 * nb][0];
-        dst[nb][4 * h + 1] = v[2 * nb][1];
-        dst[nb][4 * h + 2] = v[2 * nb + 1][0];
-        dst[nb][4 * h + 3] = v[2 * nb + 1][1];
+        const bf16x2 lo = gelu_out(v[2 * nb], S[2 * nb]), hi = gelu_out(v[2 * nb + 1], S[2 * nb + 1]);
+        dst[nb][4 * h + 0] = lo[0];
+        dst[nb][4 * h + 1] = lo[1];
+        dst[nb][4 * h + 2] = hi[0];
+        dst[nb][4 * h + 3] = hi[1];
     }
 }
 
@@ -114,9 +123,9 @@ __device__ inline f32x4 bias4(const float *b, int ob, int g) {
 }
 
 // one 128 -> 128 layer with GELU, activations in and out as B operands
-__device__ inline void hidden_layer(const f16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
-                                    f16x8 (&act)[4][kFusedNB]) {
-    f16x8 nxt[4][kFusedNB];
+__device__ inline void hidden_layer(const bf16x8 *__restrict__ w, const float *__restrict__ b, int lane, int g,
+                                    bf16x8 (&act)[4][kFusedNB]) {
+    bf16x8 nxt[4][kFusedNB];
 #pragma unroll
     for (int ob = 0; ob < 8; ++ob) {
         f32x4 acc[kFusedNB];
@@ -125,10 +134,10 @@ __device__ inline void hidden_layer(const f16x8 *__restrict__ w, const float *__
         for (int nb = 0; nb < kFusedNB; ++nb) acc[nb] = bv;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-            const f16x8 a = w[(ob * 4 + kb) * 64 + lane];
+            const bf16x8 a = w[(ob * 4 + kb) * 64 + lane];
 #pragma unroll
             for (int nb = 0; nb < kFusedNB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, act[kb][nb], acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], acc[nb], 0, 0, 0);
         }
         gelu_block(acc, nxt[ob >> 1], ob & 1);
     }
@@ -143,7 +152,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
                                                              const float *__restrict__ fb, Src src, int64_t n) {
     __shared__ __attribute__((aligned(16))) uint16_t s_w[kFWTotal];
     __shared__ __attribute__((aligned(16))) float s_b[kFB + 3];
-    __shared__ __attribute__((aligned(16))) _Float16 s_w4[4 * 64 * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 s_w4[4 * 64 * 8];
     {
         const uint4 *w_src = reinterpret_cast<const uint4 *>(fw);
         uint4 *dst = reinterpret_cast<uint4 *>(s_w);
@@ -151,18 +160,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
         for (int i = threadIdx.x; i < kFB; i += kFusedThreads) s_b[i] = fb[i];
         // the output row as the A operand of an MFMA whose first row is W4
         // (every other row zero), k-blocks permuted as the hidden layers' are;
-        // the stored W4 values are fp16 already
+        // the stored W4 values are bf16 already
         for (int i = threadIdx.x; i < 4 * 64 * 8; i += kFusedThreads) {
             const int kb = i >> 9, l = (i >> 3) & 63, e = i & 7;
-            s_w4[i] = (l & 15) == 0 ? (_Float16)fb[3 * kHid + 32 * kb + perm_k(l >> 4, e)] : (_Float16)0.0f;
+            s_w4[i] = (l & 15) == 0 ? (__bf16)fb[3 * kHid + 32 * kb + perm_k(l >> 4, e)] : (__bf16)0.0f;
         }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
-    const f16x8 *w2 = reinterpret_cast<const f16x8 *>(s_w + kFW1);
-    const f16x8 *w3 = reinterpret_cast<const f16x8 *>(s_w + kFW1 + kFW2);
+    const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
+    const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
     const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         // keep the weight reads inside the loop (hoisting them would need
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
             xin[nb] = bf16x8{(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
                              (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
         }
-        f16x8 act[4][kFusedNB];
+        bf16x8 act[4][kFusedNB];
 #pragma unroll
         for (int ob = 0; ob < 8; ++ob) {
             const bf16x8 a = w1[ob * 64 + lane];
@@ -194,15 +203,15 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
         hidden_layer(w3, s_b + 2 * kHid, lane, g, act);
         // output row on the MFMA: row 0 of the product holds y, in register 0
         // of lanes 0-15 (sample r of each 16-sample block)
-        const f16x8 *w4 = reinterpret_cast<const f16x8 *>(s_w4);
+        const bf16x8 *w4 = reinterpret_cast<const bf16x8 *>(s_w4);
         f32x4 o[kFusedNB];
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-            const f16x8 a = w4[kb * 64 + lane];
+            const bf16x8 a = w4[kb * 64 + lane];
 #pragma unroll
-            for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, act[kb][nb], o[nb], 0, 0, 0);
+            for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], o[nb], 0, 0, 0);
         }
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) {

@@ -37,6 +37,18 @@ def _params(seed):
     return p
 
 
+# The inference kernel against the FP64 reference with bf16 at the same
+# rounding points: its GELU's sigmoid factor is a polynomial in fp16
+# arithmetic (within 2e-3 of the tanh form in units of z), so an activation
+# can land on the neighbouring bf16 value (one step, 2^-8 relative) where
+# the reference's does not.  The outcome is of the size of bf16 rounding
+# itself: on 20,000 inputs of these random networks the reference with and
+# without bf16 rounding differs by up to 2.2e-3 (rms 3e-4).  Bar: twice that.
+# (The training kernels' forward pass has the reference's GELU and keeps the
+# 2e-3 bar of FP32 against FP64 sums and rare ties.)
+INFER_TOL = 4e-3
+
+
 def test_network_forward_matches_reference(dev):
     L = _lib()
     p = _params(5)
@@ -46,10 +58,10 @@ def test_network_forward_matches_reference(dev):
         y = torch.empty(1000, device=dev)
         L.lmosem_net_forward(net, torch.as_tensor(X, device=dev), y)
         torch.cuda.synchronize()
-        ref, _ = M.forward(p, X, rounding="infer")
+        ref, _ = M.forward(p, X, bf16_round=True)
         got = y.cpu().numpy()
         print(f"max |y - ref| {np.max(np.abs(got - ref)):.2e}, max |ref| {np.max(np.abs(ref)):.2f}")
-        assert np.max(np.abs(got - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+        assert np.max(np.abs(got - ref)) <= INFER_TOL * max(1.0, np.max(np.abs(ref)))
     finally:
         L.lmosem_net_destroy(net)
 
@@ -92,9 +104,9 @@ def test_network_forward_every_workgroup_loops(dev):
     finally:
         L.lmosem_net_destroy(net)
     idx = np.concatenate([np.sort(rng.choice(n - 37, 4000, replace=False)), np.arange(n - 37, n)])
-    ref, _ = M.forward(p, X[idx], rounding="infer")
+    ref, _ = M.forward(p, X[idx], bf16_round=True)
     print(f"max |y - ref| {np.max(np.abs(got[idx] - ref)):.2e}, max |ref| {np.max(np.abs(ref)):.2f}")
-    assert np.max(np.abs(got[idx] - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(got[idx] - ref)) <= INFER_TOL * max(1.0, np.max(np.abs(ref)))
 
 
 @pytest.mark.parametrize("count", [256, 1040, 2048])   # 2048: weight gradients split over the batch
@@ -300,11 +312,12 @@ def test_far_field_composition_matches_oracle(dev):
     S0 max(exp(y) - 1e-4, 0) with y the FP64 reference network (bf16
     rounding at the GPU's points) on the oracle's input features.
 
-    Tolerance per event: 1e-4 of the exact part plus 2e-3 max(1, |y|) of each
-    far pair's term, the reference network's bound (the network test above)
-    carried through exp; and, sharper, 2e-4 relative (a rounding tie that
-    moves one activation by one bf16 step changes one pair's output by about
-    1e-3, spread over the roughly 90 far pairs of an event; measured 3e-6)."""
+    Tolerance per event: 1e-4 of the exact part plus INFER_TOL max(1, |y|) of
+    each far pair's term, the network test's bound carried through exp; and,
+    sharper, 5e-4 relative: a pair's output differs from the reference's by
+    3e-4 rms (bf16 steps where the GELU polynomial crosses a rounding
+    boundary, as in the network test), and an event's mean averages the
+    roughly 90 far pairs of the event (measured 1.4e-4)."""
     L = _lib()
     w = synth.workload("tiny")
     g = w.geom.as_dict()
@@ -339,10 +352,10 @@ def test_far_field_composition_matches_oracle(dev):
                 far_feats.append(O.surrogate_features(m1, int(pix), a, u, e))
                 far_ev.append(j)
                 far_f.append(float(act.flat[pix]))
-    y, _ = M.forward(p, np.array(far_feats), rounding="infer")
+    y, _ = M.forward(p, np.array(far_feats), bf16_round=True)
     term = np.array(far_f) * s0 * np.maximum(np.exp(y) - 1e-4, 0.0)
     far = np.bincount(far_ev, weights=term, minlength=len(got))
-    slack = np.bincount(far_ev, weights=2e-3 * np.maximum(1.0, np.abs(y)) * term, minlength=len(got))
+    slack = np.bincount(far_ev, weights=INFER_TOL * np.maximum(1.0, np.abs(y)) * term, minlength=len(got))
     ref = exact + far
     err = np.abs(got - ref)
     bound = 1e-4 * exact + slack
@@ -350,7 +363,7 @@ def test_far_field_composition_matches_oracle(dev):
           f"max rel err {float(np.max(err / ref)):.2e}; max err / bound {float(np.max(err / bound)):.3f}")
     assert np.all(far > 0) and np.all(exact > 0)
     assert np.all(err <= bound)
-    assert np.all(err <= 2e-4 * ref)
+    assert np.all(err <= 5e-4 * ref)
 
 
 def _train_c4(L, dev):

@@ -77,56 +77,3 @@ def test_bf16_rounding():
     # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: to even gives 1;
     # 1 + 3 2^-8 is a tie between 1 + 2^-7 and 1 + 2^-6: to even gives 1 + 2^-6
     np.testing.assert_array_equal(out, [1.0, 1.0, 1.0 + 2 ** -6, -2.5, 1.0 + 2 ** -7])
-
-
-def test_fp16_rounding():
-    vals = np.array([1.0, 1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11, 65504.0, 2.0 ** -24, -3.0 - 2 ** -10])
-    out = M.fp16(vals)
-    # 1 + 2^-11 is a tie between 1 and 1 + 2^-10: to even gives 1; 1 + 3 2^-11
-    # gives 1 + 2^-9; the largest finite value and the smallest subnormal
-    # stay; -3 - 2^-10 is a tie between -3 and -3 - 2^-9 (ulp 2^-9 in [2, 4)):
-    # to even gives -3
-    np.testing.assert_array_equal(out, [1.0, 1.0, 1.0 + 2 ** -9, 65504.0, 2.0 ** -24, -3.0])
-
-
-def test_inference_rounding_points():
-    """One active path through the network, every pre-activation near 8 where
-    gelu(z) = z to far below an fp16 step.  The "infer" rounding keeps the
-    input and every weight in bf16 (1 + 2^-9 becomes 1; 1 + 2^-7 stays) and
-    rounds each hidden pre-activation and activation to fp16: z3 = 8 + 2^-4
-    + 2^-9 becomes 8 + 2^-4 (fp16 step 2^-7 at 8), so that y = (8 + 2^-4)
-    (1 + 2^-7) exactly; the training rounding (bf16 activations, step 2^-4
-    at 8) gives 8 + 2^-4 before the output product too, and the unrounded
-    network neither."""
-    p = {k: np.zeros(s, np.float32) for k, s in (("W1", (8, 128)), ("b1", 128), ("W2", (128, 128)),
-                                                 ("b2", 128), ("W3", (128, 128)), ("b3", 128),
-                                                 ("W4", (128, 1)), ("b4", 1))}
-    p["W1"][0, 0] = 1 + 2 ** -9
-    p["b1"][0] = 7.0
-    p["W2"][0, 0] = 1 + 2 ** -7
-    p["b2"][0] = 2 ** -9
-    p["W3"][0, 0] = 1.0
-    p["b3"][0] = 2 ** -9
-    p["W4"][0, 0] = 1 + 2 ** -7
-    x = np.zeros((1, 8), np.float32)
-    x[0, 0] = 1 + 2 ** -9
-    y_inf, c = M.forward(p, x, rounding="infer")
-    # z1 = 8; z2 = 8 (1 + 2^-7) + 2^-9 = 8 + 2^-4 + 2^-9 -> 8 + 2^-4; the same for z3
-    assert c["h1"][0, 0] == 8.0 and c["h2"][0, 0] == 8 + 2 ** -4 and c["h3"][0, 0] == 8 + 2 ** -4
-    assert y_inf[0] == (8 + 2 ** -4) * (1 + 2 ** -7)
-    y_bf, c = M.forward(p, x, bf16_round=True)
-    assert c["h2"][0, 0] == 8 + 2 ** -4 and y_bf[0] == (8 + 2 ** -4) * (1 + 2 ** -7)
-    # inputs and W1 unrounded: z1 = (1 + 2^-9)^2 + 7, off both grids
-    y_ex, _ = M.forward(p, x)
-    z1 = (1 + 2 ** -9) ** 2 + 7
-    z2 = z1 * (1 + 2 ** -7) + 2 ** -9
-    assert abs(y_ex[0] - (z2 + 2 ** -9) * (1 + 2 ** -7)) < 1e-9
-    # an activation between fp16 and bf16 steps: 1 + 2^-9 survives fp16
-    # rounding (step 2^-10) and not bf16 rounding (step 2^-7)
-    q = {k: v.copy() for k, v in p.items()}
-    q["W1"][0, 0], q["b1"][0], q["W2"][0, 0], q["b2"][0] = 0.0, 0.0, 0.0, 4 + 2 ** -8
-    q["W3"][0, 0], q["b3"][0], q["W4"][0, 0] = 1.0, 0.0, 1.0
-    y_inf, c = M.forward(q, x, rounding="infer")
-    assert c["h2"][0, 0] == 4 + 2 ** -8
-    y_bf, c = M.forward(q, x, bf16_round=True)
-    assert c["h2"][0, 0] == 4.0
