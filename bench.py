@@ -71,7 +71,7 @@ def profiled_traffic(event_tile, pixel_tile, workload, cached=False):
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
     changed since the counters were taken or the case was not profiled."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_row_dot_brain64_cached.md" if cached else "k_forward_brain64.md")
+    path = os.path.join(ROOT, "profiles", f"k_row_dot_{workload}_cached.md" if cached else f"k_forward_{workload}.md")
     src = os.path.join(ROOT, "paper_2002_12471_amd", "csrc", "osem.hip")
     try:
         fields = {}
@@ -82,7 +82,7 @@ def profiled_traffic(event_tile, pixel_tile, workload, cached=False):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         key = ("traffic_bytes_per_launch_row_dot" if cached
                else f"traffic_bytes_per_launch_ev{event_tile}_px{pixel_tile}")
-        if workload != "brain64" or fields.get("source_sha256") != sha or key not in fields:
+        if fields.get("source_sha256") != sha or key not in fields:
             return None
         return float(fields[key])
     except (OSError, KeyError, ValueError):
