@@ -138,7 +138,8 @@ hipError_t forward_noalloc(const Geo &g, const Tables &t, const lmosem_events &e
     // order the events by (angle, position), as lmosem_forward's ingest does
     // with every event in subset 0 and one realisation
     const int64_t offs_h[2] = {0, (int64_t)n};
-    if ((e = hipMemsetAsync(counts, 0, sizeof(int) * g.n_angles, st)) != hipSuccess) return e;
+    // the per-angle counters start at zero (a fill kernel: all-zero bits)
+    if ((e = launch_fill(reinterpret_cast<float *>(counts), (size_t)g.n_angles, 0.0f, st)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(offs, offs_h, sizeof offs_h, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if ((e = launch_event_keys(g, n, 1, offs, ev.angle, ev.u_bin, 0, keys, idx, st)) != hipSuccess) return e;
     if ((e = sort_pairs(tmp, L.tmp_bytes, keys, keys2, idx, idx2, n, g.n_angles, st)) != hipSuccess) return e;
