@@ -267,7 +267,7 @@ lmosem_status lmosem_set_pixel_tile(lmosem_ctx *ctx, int32_t pixels);
  * 8, 16 and 32 events per tile, each with pixel tiles of 64, 128 and 256
  * emission pixels per workgroup (and the context's own, when the emission
  * set is narrower), the backprojection with the update that
- * adds its chunk partials for 64-1024 rows per chunk (using the set's
+ * adds its chunk partials for 64-4096 rows per chunk (using the set's
  * scratch image), and one whole iteration launched kernel by kernel against one
  * replayed as a HIP graph (iterations estimated above 50 ms are replayed
  * without that comparison); re-plans the set with the fastest choices and

@@ -1275,7 +1275,7 @@ lmosem_status lmosem_autotune(lmosem_ctx *c, lmosem_evset *s, int32_t *event_til
         if (!c->surrogate) v.fwd_waves = best_waves;
         fwd_ms = best < 3.4e38f ? best : 0.0f;
         best = 3.4e38f;
-        for (int ch : {64, 128, 256, 512, 1024}) {
+        for (int ch : {64, 128, 256, 512, 1024, 2048, 4096}) {
             if (e != hipSuccess) break;
             if ((e = plan_tiles(g, c->t, v, best_ev, ch, c->st, why)) != hipSuccess) break;
             lmosem_status ws = alloc_workspace(c, s);
