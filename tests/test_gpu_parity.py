@@ -328,3 +328,30 @@ def test_pixel_tile_plans_match_oracle(brain, dev, tmp_path, monkeypatch, waves)
     f_ref, _ = O.os_lm_mlem(H, ev["angle"], sens, 10, np.ones(len(m.support)), ns)
     ok, worst = _image_ok(got, f_ref)
     assert ok, worst
+
+
+def test_tuning_cache_lines_without_a_pixel_tile(brain, dev, tmp_path, monkeypatch):
+    # a cached choice written before the pixel tile was searched (three
+    # fields) is still used, with the context's own pixel tile
+    L, ctx, w = brain["L"], brain["ctx"], brain["w"]
+    ev = synth.workload_events(w, realisation=7, n_events=2000)
+    evd = L.events_to_device(ev, dev)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LMOSEM_TUNE_CACHE", str(cache))
+    first = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        L.lmosem_autotune(ctx.handle, first)
+        default_waves = L.lmosem_evset_plan(first)["pixel_waves"]
+    finally:
+        L.lmosem_events_free(first)
+    key = cache.read_text().splitlines()[-1].split("|")[0]
+    cache.write_text(f"{key}|16 512 0\n")
+    evs = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        assert L.lmosem_autotune(ctx.handle, evs) == (16, 512, 0)
+        plan = L.lmosem_evset_plan(evs)
+        assert plan["event_tile"] == 16 and plan["chunk_rows"] == 512 and plan["graphs"] == 0
+        assert plan["pixel_waves"] == min(4, (len(brain["m"].support) + 63) // 64)
+        assert default_waves in (1, 2, 4)
+    finally:
+        L.lmosem_events_free(evs)
