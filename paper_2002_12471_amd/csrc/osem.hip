@@ -269,8 +269,11 @@ __device__ inline int xcd_logical(int p, int n) {
     return x * m + min(x, rem) + k;
 }
 
+// (the 8-event kernel fits 64 VGPRs without spilling: eight waves per SIMD,
+// measured 1-2 % faster than the seven its unbounded allocation allows; the
+// wider tiles spill when pressed below their own counts)
 template <int EV>
-__global__ __launch_bounds__(256) void k_forward(Geo g, const Tile *__restrict__ tiles, int n_tiles,
+__global__ __launch_bounds__(256, EV == 8 ? 8 : 1) void k_forward(Geo g, const Tile *__restrict__ tiles, int n_tiles,
                                                  const float2 *__restrict__ T,
                                                  const double *__restrict__ us_sorted,
                                                  const float *__restrict__ su,
