@@ -122,9 +122,21 @@ __device__ float4 column(const Geo &g, const SurrTables &st, int a, double u, in
     return make_float4((float)d_in, (float)d_out, ck * (float)g.dx, hit ? 1.0f : 0.0f);
 }
 
+// k / d for 0 <= k <= 2^24 (exact in float; pixel indices of grids up to
+// 4096 x 4096, pair indices of a batch) through a float reciprocal: the
+// estimate's relative error is below 2^-23, so it is off by at most one,
+// which one comparison each way corrects
+__device__ inline int div_small(int k, int d, float inv_d) {
+    int qt = (int)((float)k * inv_d);
+    qt += (qt + 1) * d <= k ? 1 : 0;
+    qt -= qt * d > k ? 1 : 0;
+    return qt;
+}
+
 __device__ inline void pixel_frame(const Geo &g, const SurrTables &st, int q, int a, double &uq, double &dq) {
     const int pix = st.p_pix[q];
-    const double cx = ((pix % g.nx) - 0.5 * (g.nx - 1)) * g.dx, cy = ((pix / g.nx) - 0.5 * (g.ny - 1)) * g.dx;
+    const int py = div_small(pix, g.nx, 1.0f / (float)g.nx), px = pix - py * g.nx;
+    const double cx = (px - 0.5 * (g.nx - 1)) * g.dx, cy = (py - 0.5 * (g.ny - 1)) * g.dx;
     const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
     uq = cx * -ny + cy * nx;
     dq = nx * cx + ny * cy;
@@ -135,10 +147,11 @@ __device__ inline void features(const Geo &g, const SurrTables &st, int q, int a
     double uq, dq;
     pixel_frame(g, st, q, a, uq, dq);
     const bool hit = col.w > 0.5f;
-    x[0] = (float)((u - uq) / 2.0);
-    x[1] = (float)((e - 130.0) / 30.0);
-    x[2] = hit ? (float)(((double)col.x - dq) / 10.0) : 0.0f;
-    x[3] = hit ? (float)(((double)col.y - dq) / 10.0) : 0.0f;
+    // (scales as FP64 products: within an FP64 rounding of the quotients)
+    x[0] = (float)((u - uq) * 0.5);
+    x[1] = (float)((e - 130.0) * (1.0 / 30.0));
+    x[2] = hit ? (float)(((double)col.x - dq) * 0.1) : 0.0f;
+    x[3] = hit ? (float)(((double)col.y - dq) * 0.1) : 0.0f;
     x[4] = col.z / 2.0f;
     x[5] = st.Ldet[(size_t)a * g.n_p + q];
     x[6] = st.Lback[(size_t)a * g.n_p + q];
@@ -202,9 +215,10 @@ __global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_
 __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
                              const float *__restrict__ se, const float4 *__restrict__ col, int row_base, int j0,
                              int rows, uint16_t *__restrict__ X) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch < 2^31
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch <= 2^22
     if (k >= rows * g.n_q) return;
-    const int jr = j0 + k / g.n_q, q = k % g.n_q;
+    const int lr = div_small(k, g.n_q, 1.0f / (float)g.n_q);
+    const int jr = j0 + lr, q = k - lr * g.n_q;
     const int j = row_base + jr;   // index into the sorted events
     const int a = ev_angle[j];
     const double u = ((double)su[j] - 0.5 * g.n_bins) * g.bin_cm;
