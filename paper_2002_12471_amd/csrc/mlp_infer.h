@@ -69,8 +69,9 @@ __device__ inline f16x2 clamp01(f16x2 x) {
 // tanh form, sigma(2 sqrt(2/pi) (z + 0.044715 z^3)) at z = 4 s, is
 // 1/2 + s P(s^2 - 1/2), P of degree 6 with fp16 coefficients fitted
 // (weighted least squares on |s| times the error, each coefficient rounded
-// to fp16 before the lower ones are refitted) on |s| <= 1: s times it is
-// within 5e-4 of gelu(4 s)/4, fp16 arithmetic included.
+// to fp16 before the lower ones are refitted; gelu_poly_fit.py beside this
+// file regenerates them) on |s| <= 1: s times it is within 5e-4 of
+// gelu(4 s)/4, fp16 arithmetic included.
 template <int N>
 __device__ inline void gelu_factor(const f16x2 (&s)[N], f16x2 (&S)[N]) {
     constexpr _Float16 c[7] = {0.7041015625f16, -0.67626953125f16, 0.88525390625f16, -1.1181640625f16,
