@@ -135,14 +135,14 @@ def cpu_baseline(w, act, mu, ev, n_sample=2048, seed=11):
 
 
 # The fused network per (event, pixel) pair: 384 GELUs evaluated two at a
-# time, thirteen instructions per pair of them (the conversion from the FP32
-# accumulators, the sigmoid factor's polynomial and clamps in packed fp16, two
-# mixed-precision products and the bf16 rounding; no transcendental): 2,496
-# lane-ops.  These issue at 64 lanes per CU and clock (packed fp16 measured
-# at 56-62; no dual issue), 39 CU-clocks per pair.  The MFMA work (67,840 useful flops per pair, the output row
+# time, twelve instructions per pair of them (the conversion from the FP32
+# accumulators, the sigmoid factor's polynomial in packed fp16 with its
+# clamp, two mixed-precision products and the bf16 rounding; no
+# transcendental): 2,304 lane-ops.  These issue at 64 lanes per CU and clock
+# (each kind measured at 54-58; no dual issue), 36 CU-clocks per pair.  The MFMA work (67,840 useful flops per pair, the output row
 # included; 77,824 as issued, with layer 1's inputs padded to 32 and the
 # output row's fifteen zero rows) takes 19.1 CU-clocks at 2.5 PFLOP/s.
-MLP_PK_OPS, MLP_PK_LANES = 192 * 13, 64
+MLP_PK_OPS, MLP_PK_LANES = 192 * 12, 64
 MLP_PEAK_PAIRS = N_CU * CLK / (MLP_PK_OPS / MLP_PK_LANES)
 MLP_FLOPS_PER_PAIR = 2 * (8 * 128 + 2 * 128 * 128 + 128)
 BF16_PEAK_FLOPS = 2.5e15   # MI355X dense bf16 MFMA

@@ -31,19 +31,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // which bounds the kernel).  The weights, pre-permuted into A-operand lane
 // order, the biases and the output row sit in LDS (80 KB), shared by the
 // sixteen waves of one workgroup per CU; each wave takes 32 samples per step
-// (126 VGPRs, four waves per SIMD).
+// (116 VGPRs, four waves per SIMD).
 //
 // Every hidden pre-activation is carried at a quarter of its value, s = z/4
 // (layer 1 has W1/4 and b1/4; every layer's biases are quartered), and each
 // layer stores g = gelu(4 s)/4, so that the next layer's products with the
 // plain weights give the next s; the output is 4 (W4 . g3) + b4.  Powers of
 // two scale exactly in bf16, so this is the unscaled network with its
-// activations rounded to bf16.  With s in [-1, 1] mapped to w = s^2 in
-// [0, 1], the GELU's sigmoid factor is a polynomial in packed fp16
-// arithmetic, two activations per instruction and no transcendental (the
-// clamp modifiers saturate it to 0 or 1 beyond |z| = 4, where the tanh form
-// is within 7e-5 of that); the product s times that factor is formed in FP32
-// from the two fp16 values and rounded once, to bf16.
+// activations rounded to bf16.  The GELU's sigmoid factor is a polynomial in
+// s^2 fitted on |s| <= 1 and evaluated in packed fp16 arithmetic, two
+// activations per instruction and no transcendental; beyond |s| = 1 it is
+// saturated to 0 or 1 by the clamp modifier of its last step (the tanh form
+// is within 7e-5 of that beyond |z| = 4); the product s times that factor is
+// formed in FP32 from the two fp16 values and rounded once, to bf16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
@@ -71,14 +71,18 @@ __device__ inline f16x2 clamp01(f16x2 x) {
 // (weighted least squares on |s| times the error, each coefficient rounded
 // to fp16 before the lower ones are refitted; gelu_poly_fit.py beside this
 // file regenerates them) on |s| <= 1: s times it is within 5e-4 of
-// gelu(4 s)/4, fp16 arithmetic included.
+// gelu(4 s)/4, fp16 arithmetic included.  t = s^2 - 1/2 is one fused
+// multiply-add with no clamp: past |s| = 1, P (positive and increasing there,
+// +inf once s^2 leaves fp16's range) makes |s P| exceed 1/2, and the clamp of
+// the last step saturates the factor to 0 or 1; the fit script checks this
+// in fp16 arithmetic for every fp16 value of s.
 template <int N>
 __device__ inline void gelu_factor(const f16x2 (&s)[N], f16x2 (&S)[N]) {
     constexpr _Float16 c[7] = {0.7041015625f16, -0.67626953125f16, 0.88525390625f16, -1.1181640625f16,
                                1.5205078125f16, -2.162109375f16,   1.6064453125f16};
     f16x2 t[N], q[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) t[i] = clamp01(s[i] * s[i]) - f16x2{0.5f16, 0.5f16};
+    for (int i = 0; i < N; ++i) t[i] = __builtin_elementwise_fma(s[i], s[i], f16x2{-0.5f16, -0.5f16});
 #pragma unroll
     for (int i = 0; i < N; ++i) q[i] = __builtin_elementwise_fma(f16x2{c[6], c[6]}, t[i], f16x2{c[5], c[5]});
 #pragma unroll
