@@ -342,8 +342,13 @@ __global__ void k_pack_fused(const float *__restrict__ p, uint16_t *__restrict__
 struct XSource {
     const float *X;
     float *y;
-    __device__ float4 inputs(int64_t p, int g) const { return *reinterpret_cast<const float4 *>(X + p * kIn + 4 * g); }
-    __device__ void output(int64_t p, float v) const { y[p] = v; }
+    __device__ uint2 inputs(int64_t p, int g) const {
+        const float4 v = *reinterpret_cast<const float4 *>(X + p * kIn + 4 * g);
+        return uint2{__builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v.x, v.y}, bf16x2)),
+                     __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{v.z, v.w}, bf16x2))};
+    }
+    __device__ int64_t out_base(int64_t p0) const { return p0; }
+    __device__ void output(int64_t p0, int i, float v) const { y[p0 + i] = v; }
 };
 
 // per-epoch loss: fixed-order sum of the minibatch's partial sums

@@ -4,9 +4,12 @@
 // a sample array (lmosem_net_forward) or the (event, pixel) pairs of a
 // learned-scatter sub-iteration, whose inputs are formed in the kernel.
 //
-// Src provides  __device__ float4 inputs(int64_t p, int g) const : inputs
-// 4g .. 4g+3 of sample p (g = 0, 1), and  __device__ void output(int64_t p,
-// float y) const : the network's output for sample p.
+// Src provides  __device__ uint2 inputs(int64_t p, int g) const : inputs
+// 4g .. 4g+3 of sample p (g = 0, 1) rounded to bf16, two to a word (the
+// lower-numbered input in the low half);  __device__ C out_base(int64_t p0)
+// const : for a wave's first sample p0 (the same in every lane), whatever
+// locates its output; and  __device__ void output(const C &c, int i, float y)
+// const : the network's output for sample p0 + i (0 <= i < 32).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -172,28 +175,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
         }
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const bf16x8 *w1 = reinterpret_cast<const bf16x8 *>(s_w);
     const bf16x8 *w2 = reinterpret_cast<const bf16x8 *>(s_w + kFW1);
     const bf16x8 *w3 = reinterpret_cast<const bf16x8 *>(s_w + kFW1 + kFW2);
     const int64_t n_tiles = (n + kFusedTile - 1) / kFusedTile;
+    // this lane's inputs of a tile's samples (lane groups 0 and 1 hold
+    // features 0..3 and 4..7; every other slot is zero), read one tile ahead
+    // so that their latency passes under the current tile's layers
+    uint2 in_next[kFusedNB];
+    auto read_inputs = [&](int64_t tile) {
+        const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
+#pragma unroll
+        for (int nb = 0; nb < kFusedNB; ++nb) {
+            const int64_t p = base + 16 * nb + r;
+            in_next[nb] = g < 2 && p < n ? src.inputs(p, g) : uint2{0u, 0u};
+        }
+    };
+    if ((int64_t)blockIdx.x < n_tiles) read_inputs(blockIdx.x);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         // keep the weight reads inside the loop (hoisting them would need
         // 288 registers)
         __asm__ volatile("" ::: "memory");
         const int64_t base = tile * kFusedTile + wave * 16 * kFusedNB;
-        // layer 1: the inputs as B operands (lane groups 0 and 1 hold
-        // features 0..3 and 4..7; every other slot is zero)
+        // layer 1: the inputs as B operands
         bf16x8 xin[kFusedNB];
 #pragma unroll
-        for (int nb = 0; nb < kFusedNB; ++nb) {
-            const int64_t p = base + 16 * nb + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (g < 2 && p < n) v = src.inputs(p, g);
-            xin[nb] = bf16x8{(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w,
-                             (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-        }
+        for (int nb = 0; nb < kFusedNB; ++nb)
+            xin[nb] = __builtin_bit_cast(bf16x8, uint4{in_next[nb].x, in_next[nb].y, 0u, 0u});
+        if (tile + gridDim.x < n_tiles) read_inputs(tile + gridDim.x);
         bf16x8 act[4][kFusedNB];
 #pragma unroll
         for (int ob = 0; ob < 8; ++ob) {
@@ -218,10 +229,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_infer(const uint16_t *__r
 #pragma unroll
             for (int nb = 0; nb < kFusedNB; ++nb) o[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kb][nb], o[nb], 0, 0, 0);
         }
+        const auto oc = src.out_base(base);
 #pragma unroll
         for (int nb = 0; nb < kFusedNB; ++nb) {
-            const int64_t p = base + 16 * nb + r;
-            if (g == 0 && p < n) src.output(p, fmaf(1.0f / kActScale, o[nb][0], s_b[4 * kHid]));
+            const int i = 16 * nb + r;
+            if (g == 0 && i < n - base) src.output(oc, i, fmaf(1.0f / kActScale, o[nb][0], s_b[4 * kHid]));
         }
     }
 }

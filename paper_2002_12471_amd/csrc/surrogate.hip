@@ -242,18 +242,28 @@ struct PairSource {
     float *H;
     int j0, n_q, n_qpad;
     float s0, inv_nq;   // inv_nq = 1 / n_q: pair -> (row, pixel) without an integer division
-    __device__ float4 inputs(int64_t p, int gi) const {
-        const uint2 v = *reinterpret_cast<const uint2 *>(X + p * 8 + 4 * gi);
-        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
-                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
-    }
-    __device__ void output(int64_t p, float y) const {
-        const int k = (int)p;   // < 2^22 pairs per batch: exact in FP32, and the quotient is off by at most one
+    __device__ uint2 inputs(int64_t p, int gi) const { return *reinterpret_cast<const uint2 *>(X + p * 8 + 4 * gi); }
+    // a wave's first pair as the start of its row of H and its pixel; the
+    // wave's 32 pairs then step along the row and on into the next rows
+    struct Out {
+        int64_t row;
+        int q;
+    };
+    __device__ Out out_base(int64_t p0) const {
+        const int k = (int)p0;   // < 2^22 pairs per batch: exact in FP32, and the quotient is off by at most one
         int lr = (int)((float)k * inv_nq);
         lr += (lr + 1) * n_q <= k ? 1 : 0;
         lr -= lr * n_q > k ? 1 : 0;
-        const int q = k - lr * n_q;
-        H[(size_t)(j0 + lr) * n_qpad + q] = s0 * fmaxf(__expf(y) - kTargetFloor, 0.0f);
+        return Out{(int64_t)(j0 + lr) * n_qpad, k - lr * n_q};
+    }
+    __device__ void output(const Out &o, int i, float y) const {
+        int64_t row = o.row;
+        int q = o.q + i;
+        while (q >= n_q) {   // once at most when n_q >= 32
+            q -= n_q;
+            row += n_qpad;
+        }
+        H[row + q] = s0 * fmaxf(__expf(y) - kTargetFloor, 0.0f);
     }
 };
 

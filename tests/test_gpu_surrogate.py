@@ -303,7 +303,8 @@ def test_surrogate_rows_do_not_depend_on_batching(dev):
         L.lmosem_net_destroy(net)
 
 
-def test_far_field_composition_matches_oracle(dev):
+@pytest.mark.parametrize("emission", ["support", "five"])
+def test_far_field_composition_matches_oracle(dev, emission):
     """A learned-scatter context with a fixed random network against the
     oracle's composition of the same row (Eq. 8's denominator on the
     surrogate path): for every emission pixel q of every event, the exact
@@ -317,16 +318,28 @@ def test_far_field_composition_matches_oracle(dev):
     sharper, 5e-4 relative: a pair's output differs from the reference's by
     3e-4 rms (bf16 steps where the GELU polynomial crosses a rounding
     boundary, as in the network test), and an event's mean averages the
-    roughly 90 far pairs of the event (measured 1.4e-4)."""
+    roughly 90 far pairs of the event (measured 1.4e-4).
+
+    With five emission pixels every row holds five pairs, so each wave's 32
+    pairs run across seven rows; the sharper bound is not asked there (an
+    event averages at most five far pairs)."""
     L = _lib()
     w = synth.workload("tiny")
     g = w.geom.as_dict()
     act, mu = synth.phantom(w)
     ev = synth.workload_events(w, realisation=31, n_events=96)
+    sup = np.flatnonzero((mu.ravel() > 0) & (act.ravel() > 0))
+    mask = None
+    if emission == "five":
+        sup = sup[np.linspace(0, len(sup) - 1, 5).astype(int)]
+        mask = np.zeros(mu.shape, np.float32)
+        mask.flat[sup] = 1.0
     p = _params(21)
     net = L.lmosem_net_create(p)
     try:
-        ctx = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev))
+        ctx = L.Context(dict(g, scatter_model=2), torch.as_tensor(mu, device=dev),
+                        emission=None if mask is None else torch.as_tensor(mask, device=dev))
+        assert ctx.stats()["n_emission"] == (len(sup) if mask is not None else ctx.stats()["n_support"])
         L.lmosem_set_surrogate(ctx.handle, net)
         got = ctx.forward(L.events_to_device(ev, dev), torch.as_tensor(act, device=dev)).double().cpu().numpy()
         ctx.close()
@@ -338,7 +351,6 @@ def test_far_field_composition_matches_oracle(dev):
     sig_e = float(g["fwhm_e_kev"]) / (2 * np.sqrt(2 * np.log(2)))
     s0 = 1.0 / (dx * sig_e)
     idx = (np.arange(n) - (n - 1) / 2) * dx
-    sup = np.flatnonzero((mu.ravel() > 0) & (act.ravel() > 0))
     exact = np.zeros(len(got))
     far_feats, far_ev, far_f = [], [], []
     for j in range(len(got)):
@@ -361,9 +373,12 @@ def test_far_field_composition_matches_oracle(dev):
     bound = 1e-4 * exact + slack
     print(f"{len(far_ev)} far pairs; far share of the means {float(np.mean(far / ref)):.2f}; "
           f"max rel err {float(np.max(err / ref)):.2e}; max err / bound {float(np.max(err / bound)):.3f}")
-    assert np.all(far > 0) and np.all(exact > 0)
     assert np.all(err <= bound)
-    assert np.all(err <= 5e-4 * ref)
+    if emission == "support":
+        assert np.all(far > 0) and np.all(exact > 0)
+        assert np.all(err <= 5e-4 * ref)
+    else:
+        assert np.any(far > 0) and np.any(exact > 0) and np.all(ref > 0)
 
 
 def _train_c4(L, dev):
