@@ -398,10 +398,13 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
         const PairSource src{X, H, j0, g.n_q, g.n_qpad, (float)(1.0 / (g.dx * g.sig_e)), 1.0f / (float)g.n_q};
         auto run_net = [&]() { return launch_mlp_pairs(net, src, pairs, st); };
         if ((e = wrap_net ? (*wrap_net)(run_net) : run_net()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_surr_near, dim3((unsigned)nr), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
-                           ev_angle, su, se, efac, rr, row_base, j0, nr, H);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // the near field of every row in one launch, over the network's values
+    // (one block per row: a launch per batch of rows left most of the
+    // GPU's block slots empty)
+    hipLaunchKernelGGL(k_surr_near, dim3((unsigned)rows), dim3(256), 0, st, g, s, t.band, t.band_w, t.band_lo,
+                       ev_angle, su, se, efac, rr, row_base, 0, rows, H);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_row_mean, dim3(rows), dim3(64), 0, st, g, rrange, n_real, rows, H, f, pmean);
     return hipGetLastError();
 }
