@@ -381,6 +381,9 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
                           int row_base, int rows, float *H, float *pmean, float *col, uint16_t *X,
                           int64_t pair_cap, hipStream_t st, const LaunchWrap *wrap_net) {
     if (rows <= 0) return hipSuccess;
+    // the network's output walks a wave's pairs along rows of n_q pixels
+    // (contexts never have an empty emission set; this keeps that walk finite)
+    if (g.n_q <= 0) return hipErrorInvalidValue;
     SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
     float4 *col4 = reinterpret_cast<float4 *>(col);
     int2 *rr = reinterpret_cast<int2 *>(col4 + rows);   // the workspace holds 6 words per event
