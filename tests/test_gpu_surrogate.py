@@ -66,6 +66,26 @@ def test_network_forward_matches_reference(dev):
         L.lmosem_net_destroy(net)
 
 
+@pytest.mark.parametrize("n", [1, 17, 32, 33, 511, 512, 513, 1025])
+def test_network_forward_tile_boundaries(dev, n):
+    # sizes around one wave's 32 samples and one workgroup's 512: partial
+    # waves and tiles, the inputs read a tile ahead, the last outputs
+    L = _lib()
+    p = _params(7)
+    X = np.random.default_rng(n).normal(size=(n, 8)).astype(np.float32)
+    net = L.lmosem_net_create(p)
+    try:
+        y = torch.full((n + 1,), -7.0, device=dev)   # one guard element past the end
+        L.lmosem_net_forward(net, torch.as_tensor(X, device=dev), y[:n])
+        torch.cuda.synchronize()
+        ref, _ = M.forward(p, X, bf16_round=True)
+        got = y.cpu().numpy()
+        assert got[n] == -7.0
+        assert np.max(np.abs(got[:n] - ref)) <= INFER_TOL * max(1.0, np.max(np.abs(ref)))
+    finally:
+        L.lmosem_net_destroy(net)
+
+
 def test_training_forward_matches_reference(dev):
     # the training kernels' forward pass (bf16 throughout)
     L = _lib()
