@@ -34,7 +34,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // which bounds the kernel).  The weights, pre-permuted into A-operand lane
 // order, the biases and the output row sit in LDS (80 KB), shared by the
 // sixteen waves of one workgroup per CU; each wave takes 32 samples per step
-// (116 VGPRs, four waves per SIMD).
+// (118 VGPRs, four waves per SIMD).
 //
 // Every hidden pre-activation is carried at a quarter of its value, s = z/4
 // (layer 1 has W1/4 and b1/4; every layer's biases are quartered), and each
