@@ -56,6 +56,7 @@ struct SurrTables {
     const int *s_sorted;         // [n_angles][n_p]
     const double *us_sorted;     // [n_angles][n_p]
     const float *mu_sorted;      // [n_angles][n_p]
+    float inv_nx, inv_nq;        // 1 / nx and 1 / n_q, rounded to FP32 on the host
 };
 
 // Column features of the detector line {r : r . t_a = u}: its extent inside
@@ -135,7 +136,7 @@ __device__ inline int div_small(int k, int d, float inv_d) {
 
 __device__ inline void pixel_frame(const Geo &g, const SurrTables &st, int q, int a, double &uq, double &dq) {
     const int pix = st.p_pix[q];
-    const int py = div_small(pix, g.nx, 1.0f / (float)g.nx), px = pix - py * g.nx;
+    const int py = div_small(pix, g.nx, st.inv_nx), px = pix - py * g.nx;
     const double cx = (px - 0.5 * (g.nx - 1)) * g.dx, cy = (py - 0.5 * (g.ny - 1)) * g.dx;
     const double nx = st.cs[2 * a], ny = st.cs[2 * a + 1];
     uq = cx * -ny + cy * nx;
@@ -217,7 +218,7 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_an
                              int rows, uint16_t *__restrict__ X) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch <= 2^22
     if (k >= rows * g.n_q) return;
-    const int lr = div_small(k, g.n_q, 1.0f / (float)g.n_q);
+    const int lr = div_small(k, g.n_q, st.inv_nq);
     const int jr = j0 + lr, q = k - lr * g.n_q;
     const int j = row_base + jr;   // index into the sorted events
     const int a = ev_angle[j];
@@ -228,9 +229,8 @@ __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_an
     uint4 packed;
     uint32_t *w = reinterpret_cast<uint32_t *>(&packed);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        w[i] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * i]) |
-               ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x[2 * i + 1]) << 16);
+    for (int i = 0; i < 4; ++i)   // two inputs per word, the lower-numbered in the low half
+        w[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x[2 * i], x[2 * i + 1]}, bf16x2));
     reinterpret_cast<uint4 *>(X)[k] = packed;
 }
 
@@ -368,7 +368,8 @@ hipError_t surrogate_samples(const Geo &g, const Tables &t, const int32_t *pixel
                              const float *u_bin, const float *energy, int64_t n, float *X, float *target,
                              float *scatter, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted,
+                 t.mu_sorted, 1.0f / (float)g.nx, 1.0f / (float)g.n_q};
     hipLaunchKernelGGL(k_surr_samples, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, g, s, t.p_pix + g.n_p,
                        t.Ld, t.Bt, pixel, angle, u_bin, energy, n, X, target, scatter);
     return hipGetLastError();
@@ -384,7 +385,8 @@ hipError_t surrogate_rows(const Geo &g, const Tables &t, Net *net, const int *ev
     // the network's output walks a wave's pairs along rows of n_q pixels
     // (contexts never have an empty emission set; this keeps that walk finite)
     if (g.n_q <= 0) return hipErrorInvalidValue;
-    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted, t.mu_sorted};
+    SurrTables s{t.Ldet, t.Lback, t.prim, t.p_pix, t.mu, t.cs, t.s_sorted, t.us_sorted,
+                 t.mu_sorted, 1.0f / (float)g.nx, 1.0f / (float)g.n_q};
     float4 *col4 = reinterpret_cast<float4 *>(col);
     int2 *rr = reinterpret_cast<int2 *>(col4 + rows);   // the workspace holds 6 words per event
     hipError_t e;
