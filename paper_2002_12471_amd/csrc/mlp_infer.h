@@ -2,7 +2,8 @@
 // 128 -> 128 -> 1, GELU in its tanh form, bf16 MFMA with FP32 accumulation),
 // as a template over where its inputs come from and where its outputs go:
 // a sample array (lmosem_net_forward) or the (event, pixel) pairs of a
-// learned-scatter sub-iteration, whose inputs are formed in the kernel.
+// learned-scatter sub-iteration, whose bf16 inputs a kernel of their own
+// formed beforehand.
 //
 // Src provides  __device__ uint2 inputs(int64_t p, int g) const : inputs
 // 4g .. 4g+3 of sample p (g = 0, 1) rounded to bf16, two to a word (the
