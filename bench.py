@@ -144,6 +144,13 @@ def cpu_baseline(w, act, mu, ev, n_sample=2048, seed=11):
 # output row's fifteen zero rows) takes 19.1 CU-clocks at 2.5 PFLOP/s.
 MLP_PK_OPS, MLP_PK_LANES = 192 * 12, 64
 MLP_PEAK_PAIRS = N_CU * CLK / (MLP_PK_OPS / MLP_PK_LANES)
+# The bound the measured issue rates set: the kernel's whole vector-ALU work
+# per pair as the SQ counters count it (2,436 lane-ops: the GELUs plus the
+# input words, the output and the addressing) and its 4.75 MFMA issues, one
+# issue slot of 64 lanes each, at the 57 lanes per clock and CU that every
+# instruction kind the GELU uses was probed to issue at.
+MLP_VALU_LANE_OPS, MLP_MFMA_ISSUES, MLP_PROBED_LANES = 2436, 4.75, 57
+MLP_PRACTICAL_PAIRS = N_CU * CLK / ((MLP_VALU_LANE_OPS + 64 * MLP_MFMA_ISSUES) / MLP_PROBED_LANES)
 MLP_FLOPS_PER_PAIR = 2 * (8 * 128 + 2 * 128 * 128 + 128)
 BF16_PEAK_FLOPS = 2.5e15   # MI355X dense bf16 MFMA
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
@@ -312,6 +319,10 @@ def surrogate_compare(L, torch, np, synth, large, epochs, steps, warm, full):
             "per_unit": f"one (event, emission pixel) pair = {MLP_PK_OPS} VALU lane-ops for its 384 GELUs "
                         f"(packed fp16 polynomial, bf16 result) at {MLP_PK_LANES} lanes/clk/CU",
             "frac_published_bf16": pairs_live * MLP_FLOPS_PER_PAIR / BF16_PEAK_FLOPS,
+            "frac_practical": pairs_live / MLP_PRACTICAL_PAIRS,
+            "practical_note": f"{MLP_PRACTICAL_PAIRS / 1e9:.2f} Gpair/s: {MLP_VALU_LANE_OPS} VALU lane-ops and "
+                              f"{MLP_MFMA_ISSUES} MFMA issues per pair (SQ counters) at the probed "
+                              f"{MLP_PROBED_LANES} lanes/clk/CU",
             "units_per_launch": net_stats["network_pairs"] / max(1, net_stats["network_launches"]),
             "avg_launch_us": net_stats["network_ms"] * 1e3 / max(1, net_stats["network_launches"]),
             "launches_timed": net_stats["network_launches"]},
