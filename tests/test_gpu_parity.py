@@ -184,6 +184,31 @@ def brain(dev):
     return dict(L=L, w=w, g=g, act=act, mu=mu, ev=ev, m=m, ctx=ctx, evd=L.events_to_device(ev, dev))
 
 
+@pytest.fixture(scope="module")
+def brain_sparse(brain):
+    # about three events per angle: a tile's events spread over the whole
+    # detector, so its path ends take many staging passes of 128 ranks
+    m, w = brain["m"], brain["w"]
+    ev = synth.workload_events(w, realisation=9, n_events=400)
+    ref = m.system_matrix(ev) @ brain["act"].ravel()[m.support].astype(np.float64)
+    return dict(ev=ev, ref=ref)
+
+
+@pytest.mark.parametrize("tile,pixels", [(8, 64), (16, 64), (32, 64), (8, 256), (16, 256), (32, 256)])
+def test_brain_sparse_tiles_match_oracle(brain, brain_sparse, dev, tile, pixels):
+    L, ctx = brain["L"], brain["ctx"]
+    ctx.set_tuning(tile, pixels)
+    try:
+        got = ctx.forward(L.events_to_device(brain_sparse["ev"], dev),
+                          torch.as_tensor(brain["act"], device=dev)).cpu().numpy()
+    finally:
+        ctx.set_tuning(0)
+    ref = brain_sparse["ref"]
+    live = ref > 0
+    assert live.sum() >= 0.95 * len(ref)
+    assert np.max(_rel(got[live], ref[live])) <= 1e-4 and np.all(got[~live] == 0)
+
+
 def test_sensitivity_brain(brain):
     m, ctx = brain["m"], brain["ctx"]
     for subset in (0, 5):
