@@ -380,3 +380,39 @@ def test_tuning_cache_lines_without_a_pixel_tile(brain, dev, tmp_path, monkeypat
         assert default_waves in (1, 2, 4)
     finally:
         L.lmosem_events_free(evs)
+
+
+@pytest.mark.parametrize("chunk", [64, 4096])
+def test_backprojection_chunk_extremes_match_oracle(brain, dev, tmp_path, monkeypatch, chunk):
+    # the smallest and largest backprojection chunks the autotuner may pick,
+    # forced through the tuning cache: 64 rows splits each subset's 250 rows
+    # into four chunks summed by the update, 4096 leaves one; 10 iterations
+    # of OS-LM-MLEM against the oracle
+    L, m, ctx, w = brain["L"], brain["m"], brain["ctx"], brain["w"]
+    ev = synth.workload_events(w, realisation=8, n_events=2000)
+    evd = L.events_to_device(ev, dev)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LMOSEM_TUNE_CACHE", str(cache))
+    first = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        L.lmosem_autotune(ctx.handle, first)
+    finally:
+        L.lmosem_events_free(first)
+    key = cache.read_text().splitlines()[-1].split("|")[0]
+    cache.write_text(f"{key}|8 {chunk} 0 1\n")
+    evs = L.lmosem_events_load(ctx.handle, evd)
+    try:
+        assert L.lmosem_autotune(ctx.handle, evs) == (8, chunk, 0)
+        assert L.lmosem_evset_plan(evs)["chunk_rows"] == chunk
+        img = torch.as_tensor((brain["mu"] > 0).astype(np.float32), device=dev).contiguous()
+        L.lmosem_iterate(ctx.handle, evs, 10, img)
+        torch.cuda.synchronize()
+        got = img.cpu().numpy().ravel()[m.support]
+    finally:
+        L.lmosem_events_free(evs)
+    H = m.system_matrix(ev)
+    ns = brain["g"]["n_subsets"]
+    sens = np.stack([m.sensitivity(i) for i in range(ns)])
+    f_ref, _ = O.os_lm_mlem(H, ev["angle"], sens, 10, np.ones(len(m.support)), ns)
+    ok, worst = _image_ok(got, f_ref)
+    assert ok, worst
