@@ -84,7 +84,7 @@ Geo set_geo(const lmosem_ctx *c, const lmosem_evset *s) {
     return g;
 }
 
-constexpr int64_t kPairCap = 1 << 22;   // (event, pixel) pairs per surrogate network batch (64 MB of inputs)
+constexpr int64_t kPairCap = 1 << 23;   // (event, pixel) pairs per surrogate network batch (128 MB of inputs)
 
 lmosem_status set_err(lmosem_ctx *c, lmosem_status s, const std::string &msg) {
     if (c) {

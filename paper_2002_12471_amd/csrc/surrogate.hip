@@ -216,7 +216,7 @@ __global__ void k_event_column(Geo g, SurrTables st, const int *__restrict__ ev_
 __global__ void k_surr_pairs(Geo g, SurrTables st, const int *__restrict__ ev_angle, const float *__restrict__ su,
                              const float *__restrict__ se, const float4 *__restrict__ col, int row_base, int j0,
                              int rows, uint16_t *__restrict__ X) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch <= 2^22
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;   // pairs per launch <= 2^23
     if (k >= rows * g.n_q) return;
     const int lr = div_small(k, g.n_q, st.inv_nq);
     const int jr = j0 + lr, q = k - lr * g.n_q;
@@ -250,7 +250,7 @@ struct PairSource {
         int q;
     };
     __device__ Out out_base(int64_t p0) const {
-        const int k = (int)p0;   // < 2^22 pairs per batch: exact in FP32, and the quotient is off by at most one
+        const int k = (int)p0;   // < 2^23 pairs per batch: exact in FP32, and the quotient is off by at most one
         int lr = (int)((float)k * inv_nq);
         lr += (lr + 1) * n_q <= k ? 1 : 0;
         lr -= lr * n_q > k ? 1 : 0;
